@@ -1,0 +1,222 @@
+/*
+ * isogs — differentiable tile rasterizer of 3-D Gaussians for isosurface
+ * visualization, native to AMD Instinct MI355X (gfx950).
+ *
+ * The paper ("Toward Distributed 3D Gaussian Splatting for High-Resolution
+ * Isosurface Visualization", Sec. III) initialises 3D-GS primitives from
+ * isosurface points, generates synthetic views on a structured orbit and
+ * trains the 3D-GS model to match them.  This C ABI exposes that training
+ * path as calls on plain pointers and sizes: orbit cameras, initialisation
+ * from points, render (forward), loss gradient, render backward and the Adam
+ * step, plus a batched hipGraph step, an autotuner and a render server.
+ *
+ * Conventions shared by every call
+ *  - Pointers documented as "device" point to HIP device memory on the
+ *    context's device; "host" pointers to ordinary host memory.
+ *  - Parameter, gradient and optimiser-state arrays are structure-of-arrays,
+ *    float32, owned by the caller:
+ *        means[3][n], log_scales[3][n], quats[4][n] (w, x, y, z),
+ *        opacity_logits[n], sh[(d+1)^2 * 3][n] with row index j*3 + c.
+ *  - Images are planar float32 [3][height][width], owned by the caller.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Device work is enqueued on it asynchronously unless stated otherwise.
+ *  - Every call returns a gs_status; none throws.  On failure the calling
+ *    thread's gs_last_error() describes the cause.  HIP runtime failures map
+ *    to GS_ERR_HIP, capacity overruns to GS_ERR_CAPACITY.
+ *  - Objects created by the library (contexts, frames, graphs, servers) are
+ *    owned by it and freed by their *_destroy / *_release call.
+ */
+#ifndef ISOGS_H
+#define ISOGS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  GS_OK = 0,
+  GS_ERR_INVALID = -1,     /* bad argument (null pointer, size out of range) */
+  GS_ERR_NOMEM = -2,       /* device memory or the context budget exhausted */
+  GS_ERR_HIP = -3,         /* a HIP runtime call failed */
+  GS_ERR_CAPACITY = -4,    /* more (Gaussian, tile) records than fit */
+  GS_ERR_UNSUPPORTED = -5, /* device is not gfx950, or option not supported */
+  GS_ERR_BUSY = -6         /* object in use (server queue full, ...) */
+} gs_status;
+
+typedef struct gs_ctx gs_ctx;
+typedef struct gs_frame gs_frame;
+typedef struct gs_graph gs_graph;
+typedef struct gs_server gs_server;
+
+/* Gaussian parameters (or gradients, or Adam moments) of one scene: device
+ * pointers into caller-owned SoA float32 arrays (layout above).  n >= 1,
+ * sh_degree in 0..3. */
+typedef struct {
+  float* means;
+  float* log_scales;
+  float* quats;
+  float* opacity_logits;
+  float* sh;
+  int64_t n;
+  int32_t sh_degree;
+  int32_t reserved;
+} gs_params;
+
+/* Pinhole camera.  R is the row-major world->camera rotation and t the
+ * translation (p_cam = R p + t); camera axes x right, y down, z forward.
+ * fx, fy, cx, cy in pixels; pixel (x, y) is sampled at (x + 0.5, y + 0.5).
+ * Gaussians with camera depth <= z_near are culled.  width, height in
+ * [1, 16384]. */
+typedef struct {
+  float R[9];
+  float t[3];
+  float fx, fy, cx, cy;
+  float z_near;
+  int32_t width, height;
+  int32_t reserved;
+} gs_camera;
+
+/* Render options.  tile in {8, 16, 32} (pixels per tile side); lds_depth in
+ * {32, 64, 128, 256} (Gaussians staged in LDS per batch; 0 = default 256,
+ * clipped to the tile's pixel count for tile 8); bg = background colour. */
+typedef struct {
+  int32_t tile;
+  int32_t lds_depth;
+  float bg[3];
+  int32_t reserved;
+} gs_render_opts;
+
+/* Adam hyper-parameters; learning rate per parameter group. */
+typedef struct {
+  float lr_means, lr_log_scales, lr_quats, lr_opacity, lr_sh_dc, lr_sh_rest;
+  float beta1, beta2, eps;
+  int32_t zero_grads; /* nonzero: gradients are cleared after use */
+} gs_adam_opts;
+
+/* Initialisation from isosurface points (Sec. III: the point cloud
+ * initialises the Gaussian primitives).  Log-scales are log_scale +
+ * U(-log_scale_jitter, +log_scale_jitter) per axis when log_scale_lo >=
+ * log_scale_hi, else U(log_scale_lo, log_scale_hi); quaternions are the
+ * identity or uniformly random; opacity logits constant; SH coefficients
+ * N(0, sh_std) (0 = all zero).  Random draws use Philox4x32-10 keyed by the
+ * seed with counter (Gaussian index, stream id, 0, 0). */
+typedef struct {
+  float log_scale;
+  float log_scale_jitter;
+  float log_scale_lo, log_scale_hi;
+  int32_t random_quats;
+  float opacity_logit;
+  float sh_std;
+  int32_t reserved;
+} gs_init_opts;
+
+/* Per-frame figures, read back to the host. */
+typedef struct {
+  int32_t n_views;
+  int32_t tile;
+  int64_t n_gaussians;
+  int64_t n_records;        /* K: (Gaussian, tile) records over all views */
+  int64_t n_visible;        /* (view, Gaussian) pairs touching >= 1 tile */
+  int64_t n_tiles;          /* tiles over all views */
+  int64_t n_pixels;         /* pixels over all views */
+  int64_t device_bytes;     /* device memory held by the frame */
+} gs_frame_stats;
+
+/* What gs_frame_export copies out (device -> caller's device buffer). */
+typedef enum {
+  GS_EXPORT_KEYS = 0,       /* uint64[K]: (global tile << 32) | float32 depth bits, sorted */
+  GS_EXPORT_VALUES = 1,     /* uint32[K]: view * n + Gaussian index, same order */
+  GS_EXPORT_RANGES = 2,     /* uint32[n_tiles][2]: [start, end) per global tile */
+  GS_EXPORT_FINAL_T = 3,    /* float[n_pixels]: transmittance left after blending */
+  GS_EXPORT_N_CONTRIB = 4,  /* uint32[n_pixels]: position + 1 of the last contributor */
+  GS_EXPORT_SCREEN_GRADS = 5, /* float[n_views][9][n]: dL/d(m_x, m_y, A, B, C, opacity, r, g, b) */
+  GS_EXPORT_SPLATS = 6,     /* float[n_views][n][12]: A, B, C, o, mx, my, -, -, r, g, b, depth */
+  GS_EXPORT_RECTS = 7       /* uint32[n_views][n][2]: tile x0 | y0 << 16, x1 | y1 << 16
+                               (x1 < x0 when the Gaussian touches no tile) */
+} gs_export;
+
+/* ------------------------------------------------------------------ core */
+
+/* Description of the calling thread's last failure (library-owned string,
+ * valid until the thread's next failing call). */
+const char* gs_last_error(void);
+
+/* Library version string, e.g. "isogs 0.1 gfx950". */
+const char* gs_version(void);
+
+/* Create a context on HIP device `device`.  mem_budget caps the device
+ * memory the library allocates for its own scratch (0 = no cap).  Fails with
+ * GS_ERR_UNSUPPORTED on a device that is not gfx950. */
+gs_status gs_ctx_create(int device, size_t mem_budget, gs_ctx** out);
+void gs_ctx_destroy(gs_ctx* ctx);
+/* Bytes of device scratch currently held by the context and its frames. */
+gs_status gs_ctx_memory(gs_ctx* ctx, size_t* in_use, size_t* peak);
+
+/* Structured orbit of look-at views (Sec. III: synthetic views "in a
+ * structured orbit"; Sec. IV: 448 views per dataset).  View i of n sits on a
+ * Fibonacci sphere of the given radius at height y = 1 - 2 (i + 0.5) / n and
+ * azimuth i * pi * (3 - sqrt 5), looking at the origin, world up +y (+z when
+ * |y| > 0.99); focal length from the vertical field of view, square pixels,
+ * principal point at the image centre, z_near 0.2.  Host only; `out` is a
+ * caller-owned host array of n_views cameras. */
+gs_status gs_orbit_cameras(int32_t n_views, float radius, float fov_y_deg,
+                           int32_t width, int32_t height, gs_camera* out);
+
+/* Gaussians from isosurface points (Sec. III).  xyz: device float32 [3][n]
+ * point coordinates.  Writes every array of `out` (device, caller-owned,
+ * sized for n and out.sh_degree): means = points, the rest per `opts`. */
+gs_status gs_init_from_points(gs_ctx* ctx, const float* xyz, int64_t n,
+                              const gs_init_opts* opts, uint64_t seed,
+                              gs_params out, void* stream);
+
+/* Forward render of n_views views (1..16) of one scene: EWA projection and
+ * SH colour, tile binning and sort, front-to-back compositing.  images[v]
+ * (device, [3][H_v][W_v]) receives view v.  `*state` receives the frame that
+ * the backward pass needs; pass a previous frame to reuse its memory, or
+ * NULL to create one (release with gs_frame_release).  The record count is
+ * read back to size the sort, so this call synchronises `stream` once. */
+gs_status gs_render_fwd(gs_ctx* ctx, gs_params params, const gs_camera* cams,
+                        int32_t n_views, float* const* images,
+                        const gs_render_opts* opts, gs_frame** state,
+                        void* stream);
+
+/* Training loss of n_views rendered images against targets and its image
+ * gradient: mean over views of (1 - lambda) L1 + lambda (1 - SSIM), SSIM with
+ * an 11x11 Gaussian window (sigma 1.5), C1 = 1e-4, C2 = 9e-4, zero padding.
+ * loss_out: device float (may be NULL); dl_dimg[v]: device [3][H_v][W_v]. */
+gs_status gs_loss_grad(gs_ctx* ctx, const float* const* rendered,
+                       const float* const* target, const gs_camera* cams,
+                       int32_t n_views, float lambda_dssim, float* loss_out,
+                       float* const* dl_dimg, void* stream);
+
+/* Backward of gs_render_fwd for the frame's views: reverse front-to-back
+ * traversal that recomputes transmittance (no per-pixel lists are stored),
+ * then the chain rule to every parameter.  dl_dimg[v] as above.  grads
+ * (device, caller-owned, same shapes as params) receive the gradient summed
+ * over the views; accumulate != 0 adds to their contents instead. */
+gs_status gs_render_bwd(gs_ctx* ctx, gs_frame* frame, gs_params params,
+                        const float* const* dl_dimg, gs_params grads,
+                        int32_t accumulate, void* stream);
+
+/* One fused, bias-corrected Adam step over every parameter group (step
+ * counts from 1).  p, m, v updated in place; g read (and cleared if
+ * opts->zero_grads). */
+gs_status gs_adam_step(gs_ctx* ctx, gs_params p, gs_params g, gs_params m,
+                       gs_params v, const gs_adam_opts* opts, int64_t step,
+                       void* stream);
+
+gs_status gs_frame_stats_get(gs_frame* frame, gs_frame_stats* out);
+/* Copy a frame buffer (see gs_export) for view `view` (-1 = all views) into
+ * the caller's device buffer dst of `bytes` bytes (must be large enough). */
+gs_status gs_frame_export(gs_frame* frame, int32_t what, int32_t view, void* dst,
+                          size_t bytes, void* stream);
+void gs_frame_release(gs_frame* frame);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ISOGS_H */

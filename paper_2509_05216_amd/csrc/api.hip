@@ -1,0 +1,665 @@
+// C ABI of the isogs library: contexts, device scratch, cameras and the
+// orchestration of the forward/backward passes on a caller's HIP stream.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <new>
+
+#include "internal.h"
+
+namespace isogs {
+
+static thread_local char g_err[1024] = "";
+
+void set_error(const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+}
+
+gs_status hip_fail(hipError_t e, const char* what) {
+  set_error("%s failed: %s", what, hipGetErrorString(e));
+  return (e == hipErrorOutOfMemory) ? GS_ERR_NOMEM : GS_ERR_HIP;
+}
+
+gs_status buf_ensure(Ctx* ctx, DevBuf& b, size_t bytes) {
+  if (bytes <= b.cap) return GS_OK;
+  size_t want = bytes + bytes / 8;
+  want = (want + 4095) & ~(size_t)4095;
+  const size_t after = ctx->in_use - b.cap + want;
+  if (ctx->budget != 0 && after > ctx->budget) {
+    set_error("device scratch budget exceeded: need %zu bytes, budget %zu", after, ctx->budget);
+    return GS_ERR_NOMEM;
+  }
+  if (b.p != nullptr) {
+    GS_HIP(hipDeviceSynchronize());  // queued work may still use the old buffer
+    GS_HIP(hipFree(b.p));
+    ctx->in_use -= b.cap;
+    b.p = nullptr;
+    b.cap = 0;
+  }
+  hipError_t e = hipMalloc(&b.p, want);
+  if (e != hipSuccess) {
+    b.p = nullptr;
+    set_error("hipMalloc(%zu) failed: %s", want, hipGetErrorString(e));
+    return GS_ERR_NOMEM;
+  }
+  b.cap = want;
+  ctx->in_use += want;
+  if (ctx->in_use > ctx->peak) ctx->peak = ctx->in_use;
+  return GS_OK;
+}
+
+void buf_free(Ctx* ctx, DevBuf& b) {
+  if (b.p != nullptr) {
+    (void)hipFree(b.p);
+    ctx->in_use -= b.cap;
+  }
+  b.p = nullptr;
+  b.cap = 0;
+}
+
+size_t Frame::bytes() const {
+  size_t s = splat.cap + rect.cap + dkey.cap + dkw[0].cap + dkw[1].cap + sidx[0].cap +
+             sidx[1].cap + clampm.cap + offs.cap + tkey[0].cap + tkey[1].cap + tval[0].cap +
+             tval[1].cap + ranges.cap + finalT.cap + ncon.cap + acc.cap + ss.hist.cap +
+             ss.partial.cap + ss.total.cap;
+  return s;
+}
+
+static void frame_free(Frame* f) {
+  Ctx* c = f->ctx;
+  DevBuf* all[] = {&f->splat,   &f->rect,    &f->dkey,    &f->dkw[0],  &f->dkw[1],
+                   &f->sidx[0], &f->sidx[1], &f->clampm,  &f->offs,    &f->tkey[0],
+                   &f->tkey[1], &f->tval[0], &f->tval[1], &f->ranges,  &f->finalT,
+                   &f->ncon,    &f->acc,     &f->ss.hist, &f->ss.partial, &f->ss.total};
+  for (DevBuf* b : all) buf_free(c, *b);
+  if (f->pinned != nullptr) (void)hipHostFree(f->pinned);
+  f->pinned = nullptr;
+}
+
+static bool valid_params(const gs_params& p, const char* what) {
+  if (p.means == nullptr || p.log_scales == nullptr || p.quats == nullptr ||
+      p.opacity_logits == nullptr || p.sh == nullptr) {
+    set_error("%s: null parameter pointer", what);
+    return false;
+  }
+  if (p.n < 1 || p.n > 0x7fffffff) {
+    set_error("%s: n = %lld out of range", what, (long long)p.n);
+    return false;
+  }
+  if (p.sh_degree < 0 || p.sh_degree > 3) {
+    set_error("%s: sh_degree %d not in 0..3", what, p.sh_degree);
+    return false;
+  }
+  return true;
+}
+
+static bool valid_camera(const gs_camera& c, int v) {
+  if (c.width < 1 || c.width > 16384 || c.height < 1 || c.height > 16384) {
+    set_error("camera %d: size %dx%d outside [1, 16384]", v, c.width, c.height);
+    return false;
+  }
+  if (!(c.fx > 0) || !(c.fy > 0) || !(c.z_near > 0)) {
+    set_error("camera %d: focal lengths and z_near must be positive", v);
+    return false;
+  }
+  return true;
+}
+
+static ParamsDev params_dev(const gs_params& p) {
+  ParamsDev d;
+  d.means = p.means;
+  d.log_scales = p.log_scales;
+  d.quats = p.quats;
+  d.logits = p.opacity_logits;
+  d.sh = p.sh;
+  d.n = (int)p.n;
+  d.sh_degree = p.sh_degree;
+  return d;
+}
+
+// Fill the view table of a frame from host cameras.
+static gs_status build_views(Frame& f, const gs_camera* cams, int nv, float* const* images,
+                             const float bg[3]) {
+  ViewTable& vt = f.vt;
+  std::memset(&vt, 0, sizeof(vt));
+  vt.n = nv;
+  vt.tile = f.tile;
+  for (int k = 0; k < 3; ++k) vt.bg[k] = bg[k];
+  long long tiles = 0, pix = 0;
+  for (int v = 0; v < nv; ++v) {
+    const gs_camera& c = cams[v];
+    CamDev& d = vt.v[v];
+    for (int k = 0; k < 9; ++k) d.R[k] = c.R[k];
+    for (int k = 0; k < 3; ++k) d.t[k] = c.t[k];
+    d.fx = c.fx;
+    d.fy = c.fy;
+    d.cx = c.cx;
+    d.cy = c.cy;
+    d.znear = c.z_near;
+    for (int k = 0; k < 3; ++k)  // camera centre -R^T t
+      d.campos[k] = (float)(-((double)c.R[0 * 3 + k] * c.t[0] + (double)c.R[1 * 3 + k] * c.t[1] +
+                              (double)c.R[2 * 3 + k] * c.t[2]));
+    d.W = c.width;
+    d.H = c.height;
+    d.tiles_x = (c.width + f.tile - 1) / f.tile;
+    d.tiles_y = (c.height + f.tile - 1) / f.tile;
+    d.tile_offset = (int)tiles;
+    d.pix_offset = pix;
+    d.image = images != nullptr ? images[v] : nullptr;
+    d.dimg = nullptr;
+    tiles += (long long)d.tiles_x * d.tiles_y;
+    pix += (long long)c.width * c.height;
+  }
+  if (tiles >= 0x7fffffffLL) {
+    set_error("too many tiles (%lld)", tiles);
+    return GS_ERR_INVALID;
+  }
+  vt.total_tiles = (int)tiles;
+  f.total_pix = pix;
+  int bits = 1;
+  while ((1LL << bits) < tiles) ++bits;
+  f.key_bits = bits;
+  return GS_OK;
+}
+
+static gs_status frame_buffers(Frame& f) {
+  Ctx* c = f.ctx;
+  const size_t vn = (size_t)f.views * (size_t)f.n;
+  gs_status st;
+#define ENS(buf, bytes)                       \
+  do {                                        \
+    st = buf_ensure(c, (buf), (bytes));       \
+    if (st != GS_OK) return st;               \
+  } while (0)
+  ENS(f.splat, vn * 48);
+  ENS(f.rect, vn * 8);
+  ENS(f.dkey, vn * 4);
+  ENS(f.dkw[0], vn * 4);
+  ENS(f.dkw[1], vn * 4);
+  ENS(f.sidx[0], vn * 4);
+  ENS(f.sidx[1], vn * 4);
+  ENS(f.clampm, vn);
+  ENS(f.offs, vn * 4);
+  ENS(f.ranges, (size_t)f.vt.total_tiles * 8);
+  ENS(f.finalT, (size_t)f.total_pix * 4);
+  ENS(f.ncon, (size_t)f.total_pix * 4);
+  const size_t acc_bytes = (size_t)f.views * 9 * (size_t)f.n * 4;
+  if (f.acc.cap < acc_bytes) {
+    ENS(f.acc, acc_bytes);
+    f.acc_zeroed = false;
+  }
+#undef ENS
+  if (f.pinned == nullptr) GS_HIP(hipHostMalloc((void**)&f.pinned, 64, hipHostMallocDefault));
+  return GS_OK;
+}
+
+static gs_status set_device(Ctx* ctx) {
+  GS_HIP(hipSetDevice(ctx->device));
+  return GS_OK;
+}
+
+}  // namespace isogs
+
+using namespace isogs;
+
+extern "C" {
+
+const char* gs_last_error(void) { return g_err; }
+
+const char* gs_version(void) { return "isogs 0.1 gfx950"; }
+
+gs_status gs_ctx_create(int device, size_t mem_budget, gs_ctx** out) {
+  if (out == nullptr) {
+    set_error("gs_ctx_create: out is null");
+    return GS_ERR_INVALID;
+  }
+  *out = nullptr;
+  int count = 0;
+  GS_HIP(hipGetDeviceCount(&count));
+  if (device < 0 || device >= count) {
+    set_error("gs_ctx_create: device %d not in [0, %d)", device, count);
+    return GS_ERR_INVALID;
+  }
+  gs_ctx* c = new (std::nothrow) gs_ctx();
+  if (c == nullptr) {
+    set_error("gs_ctx_create: out of host memory");
+    return GS_ERR_NOMEM;
+  }
+  c->device = device;
+  c->budget = mem_budget;
+  hipError_t e = hipSetDevice(device);
+  if (e == hipSuccess) e = hipGetDeviceProperties(&c->prop, device);
+  if (e != hipSuccess) {
+    delete c;
+    return hip_fail(e, "hipGetDeviceProperties");
+  }
+  if (std::strncmp(c->prop.gcnArchName, "gfx950", 6) != 0) {
+    set_error("device %d is %s; this library is built for gfx950 only", device,
+              c->prop.gcnArchName);
+    delete c;
+    return GS_ERR_UNSUPPORTED;
+  }
+  c->cu_count = c->prop.multiProcessorCount;
+  *out = c;
+  return GS_OK;
+}
+
+void gs_ctx_destroy(gs_ctx* ctx) {
+  if (ctx == nullptr) return;
+  (void)hipSetDevice(ctx->device);
+  (void)hipDeviceSynchronize();
+  free_loss_scratch(ctx);
+  delete ctx;
+}
+
+gs_status gs_ctx_memory(gs_ctx* ctx, size_t* in_use, size_t* peak) {
+  if (ctx == nullptr) {
+    set_error("gs_ctx_memory: null context");
+    return GS_ERR_INVALID;
+  }
+  if (in_use) *in_use = ctx->in_use;
+  if (peak) *peak = ctx->peak;
+  return GS_OK;
+}
+
+gs_status gs_orbit_cameras(int32_t n_views, float radius, float fov_y_deg, int32_t width,
+                           int32_t height, gs_camera* out) {
+  if (out == nullptr || n_views < 1 || !(radius > 0) || !(fov_y_deg > 0) || !(fov_y_deg < 180) ||
+      width < 1 || width > 16384 || height < 1 || height > 16384) {
+    set_error("gs_orbit_cameras: invalid arguments");
+    return GS_ERR_INVALID;
+  }
+  const double pi = 3.14159265358979323846;
+  const double f = height / (2.0 * std::tan(fov_y_deg * pi / 360.0));
+  const double golden = pi * (3.0 - std::sqrt(5.0));
+  for (int i = 0; i < n_views; ++i) {
+    const double y = 1.0 - 2.0 * (i + 0.5) / n_views;
+    const double rxz = std::sqrt(std::fmax(0.0, 1.0 - y * y));
+    const double phi = i * golden;
+    const double C[3] = {radius * rxz * std::cos(phi), radius * y, radius * rxz * std::sin(phi)};
+    const double up[3] = {0.0, std::fabs(y) > 0.99 ? 0.0 : 1.0, std::fabs(y) > 0.99 ? 1.0 : 0.0};
+    // forward = normalise(-C); right = normalise(forward x up); down = forward x right
+    double fw[3] = {-C[0], -C[1], -C[2]};
+    double ln = std::sqrt(fw[0] * fw[0] + fw[1] * fw[1] + fw[2] * fw[2]);
+    for (double& x : fw) x /= ln;
+    double rt[3] = {fw[1] * up[2] - fw[2] * up[1], fw[2] * up[0] - fw[0] * up[2],
+                    fw[0] * up[1] - fw[1] * up[0]};
+    ln = std::sqrt(rt[0] * rt[0] + rt[1] * rt[1] + rt[2] * rt[2]);
+    for (double& x : rt) x /= ln;
+    const double dn[3] = {fw[1] * rt[2] - fw[2] * rt[1], fw[2] * rt[0] - fw[0] * rt[2],
+                          fw[0] * rt[1] - fw[1] * rt[0]};
+    gs_camera& c = out[i];
+    std::memset(&c, 0, sizeof(c));
+    const double* rows[3] = {rt, dn, fw};
+    for (int r = 0; r < 3; ++r) {
+      for (int k = 0; k < 3; ++k) c.R[r * 3 + k] = (float)rows[r][k];
+      c.t[r] = (float)(-(rows[r][0] * C[0] + rows[r][1] * C[1] + rows[r][2] * C[2]));
+    }
+    c.fx = (float)f;
+    c.fy = (float)f;
+    c.cx = (float)(width / 2.0);
+    c.cy = (float)(height / 2.0);
+    c.z_near = 0.2f;
+    c.width = width;
+    c.height = height;
+  }
+  return GS_OK;
+}
+
+gs_status gs_init_from_points(gs_ctx* ctx, const float* xyz, int64_t n, const gs_init_opts* opts,
+                              uint64_t seed, gs_params out, void* stream) {
+  if (ctx == nullptr || xyz == nullptr || opts == nullptr) {
+    set_error("gs_init_from_points: null argument");
+    return GS_ERR_INVALID;
+  }
+  if (!valid_params(out, "gs_init_from_points") || out.n != n) {
+    if (out.n != n) set_error("gs_init_from_points: out.n (%lld) != n (%lld)", (long long)out.n,
+                              (long long)n);
+    return GS_ERR_INVALID;
+  }
+  gs_status st = set_device(ctx);
+  if (st != GS_OK) return st;
+  return launch_init_points(xyz, n, *opts, seed, out, (hipStream_t)stream);
+}
+
+gs_status gs_render_fwd(gs_ctx* ctx, gs_params params, const gs_camera* cams, int32_t n_views,
+                        float* const* images, const gs_render_opts* opts, gs_frame** state,
+                        void* stream) {
+  if (ctx == nullptr || cams == nullptr || images == nullptr || state == nullptr) {
+    set_error("gs_render_fwd: null argument");
+    return GS_ERR_INVALID;
+  }
+  if (!valid_params(params, "gs_render_fwd")) return GS_ERR_INVALID;
+  if (n_views < 1 || n_views > kMaxViews) {
+    set_error("gs_render_fwd: n_views %d not in [1, %d]", n_views, kMaxViews);
+    return GS_ERR_INVALID;
+  }
+  for (int v = 0; v < n_views; ++v) {
+    if (!valid_camera(cams[v], v)) return GS_ERR_INVALID;
+    if (images[v] == nullptr) {
+      set_error("gs_render_fwd: images[%d] is null", v);
+      return GS_ERR_INVALID;
+    }
+  }
+  if ((uint64_t)n_views * (uint64_t)params.n >= 0xffffffffULL) {
+    set_error("gs_render_fwd: n_views * n exceeds 2^32 - 1");
+    return GS_ERR_CAPACITY;
+  }
+  int tile = 16, depth = 256;
+  float bg[3] = {0.f, 0.f, 0.f};
+  if (opts != nullptr) {
+    tile = opts->tile;
+    depth = opts->lds_depth == 0 ? 256 : opts->lds_depth;
+    for (int k = 0; k < 3; ++k) bg[k] = opts->bg[k];
+  }
+  if (tile != 8 && tile != 16 && tile != 32) {
+    set_error("gs_render_fwd: tile %d not in {8, 16, 32}", tile);
+    return GS_ERR_INVALID;
+  }
+  if (depth != 32 && depth != 64 && depth != 128 && depth != 256) {
+    set_error("gs_render_fwd: lds_depth %d not in {32, 64, 128, 256}", depth);
+    return GS_ERR_INVALID;
+  }
+  if (tile == 8 && depth > 64) depth = 64;
+  gs_status st = set_device(ctx);
+  if (st != GS_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+
+  gs_frame* fr = *state;
+  const bool fresh = (fr == nullptr);
+  if (fresh) {
+    fr = new (std::nothrow) gs_frame();
+    if (fr == nullptr) {
+      set_error("gs_render_fwd: out of host memory");
+      return GS_ERR_NOMEM;
+    }
+    fr->ctx = ctx;
+  } else if (fr->ctx != ctx) {
+    set_error("gs_render_fwd: frame belongs to another context");
+    return GS_ERR_INVALID;
+  }
+  Frame& f = *fr;
+  f.n = params.n;
+  f.views = n_views;
+  f.tile = tile;
+  f.depth = depth;
+  f.sh_degree = params.sh_degree;
+  f.K = 0;
+  st = build_views(f, cams, n_views, images, bg);
+  if (st == GS_OK) st = frame_buffers(f);
+  if (st != GS_OK) {
+    if (fresh) {
+      frame_free(fr);
+      delete fr;
+    }
+    return st;
+  }
+  if (!f.acc_zeroed) {
+    st = launch_fill_u32(f.acc.p, 0u, (size_t)f.views * 9 * (size_t)f.n, s);
+    if (st != GS_OK) return st;
+    f.acc_zeroed = true;
+  }
+  *state = fr;
+  const ParamsDev pd = params_dev(params);
+  const uint32_t vn = (uint32_t)((size_t)f.views * (size_t)f.n);
+
+  // 1. projection + SH
+  st = launch_preprocess_fwd(pd, f.vt, f, s);
+  if (st != GS_OK) return st;
+  // 2. (view, Gaussian) entries in (depth bits, index) order
+  int in_b = 0;
+  st = sort_pairs_u32(ctx, f.ss, (const uint32_t*)f.dkey.p, nullptr, (uint32_t*)f.dkw[0].p,
+                      (uint32_t*)f.sidx[0].p, (uint32_t*)f.dkw[1].p, (uint32_t*)f.sidx[1].p, vn,
+                      nullptr, 32, &in_b, s);
+  if (st != GS_OK) return st;
+  f.sidx_sel = in_b;
+  const uint32_t* sidx = (const uint32_t*)f.sidx[in_b].p;
+  // 3. record offsets and the total K (read back to size the record buffers)
+  st = buf_ensure(ctx, f.ss.total, 16);
+  if (st != GS_OK) return st;
+  st = scan_tile_counts(ctx, f.ss, sidx, (const uint2*)f.rect.p, vn, (uint32_t*)f.offs.p,
+                        (uint64_t*)f.ss.total.p, s);
+  if (st != GS_OK) return st;
+  GS_HIP(hipMemcpyAsync(f.pinned, f.ss.total.p, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+  GS_HIP(hipStreamSynchronize(s));
+  const uint64_t K = f.pinned[0];
+  if (K >= 0xffffffffULL) {
+    set_error("gs_render_fwd: %llu (Gaussian, tile) records exceed 2^32 - 1",
+              (unsigned long long)K);
+    return GS_ERR_CAPACITY;
+  }
+  f.K = (int64_t)K;
+  for (int k = 0; k < 2; ++k) {
+    st = buf_ensure(ctx, f.tkey[k], (size_t)(K + 1) * 4);
+    if (st == GS_OK) st = buf_ensure(ctx, f.tval[k], (size_t)(K + 1) * 4);
+    if (st != GS_OK) return st;
+  }
+  // 4. records in depth order, then the stable sort on the tile digits
+  st = launch_emit(f.vt, f, sidx, vn, s);
+  if (st != GS_OK) return st;
+  st = sort_pairs_u32(ctx, f.ss, (const uint32_t*)f.tkey[0].p, (const uint32_t*)f.tval[0].p,
+                      (uint32_t*)f.tkey[1].p, (uint32_t*)f.tval[1].p, (uint32_t*)f.tkey[0].p,
+                      (uint32_t*)f.tval[0].p, (uint32_t)K, nullptr, f.key_bits, &in_b, s);
+  if (st != GS_OK) return st;
+  f.tkey_sel = (K == 0) ? 0 : (in_b ? 0 : 1);
+  // 5. per-tile ranges, 6. compositing
+  st = launch_ranges(f, s);
+  if (st != GS_OK) return st;
+  return launch_blend_fwd(f.vt, f, s);
+}
+
+gs_status gs_loss_grad(gs_ctx* ctx, const float* const* rendered, const float* const* target,
+                       const gs_camera* cams, int32_t n_views, float lambda_dssim,
+                       float* loss_out, float* const* dl_dimg, void* stream) {
+  if (ctx == nullptr || rendered == nullptr || target == nullptr || cams == nullptr) {
+    set_error("gs_loss_grad: null argument");
+    return GS_ERR_INVALID;
+  }
+  if (n_views < 1 || n_views > kMaxViews) {
+    set_error("gs_loss_grad: n_views %d not in [1, %d]", n_views, kMaxViews);
+    return GS_ERR_INVALID;
+  }
+  if (!(lambda_dssim >= 0.f && lambda_dssim <= 1.f)) {
+    set_error("gs_loss_grad: lambda %g not in [0, 1]", (double)lambda_dssim);
+    return GS_ERR_INVALID;
+  }
+  int W[kMaxViews], H[kMaxViews];
+  for (int v = 0; v < n_views; ++v) {
+    if (!valid_camera(cams[v], v)) return GS_ERR_INVALID;
+    if (rendered[v] == nullptr || target[v] == nullptr) {
+      set_error("gs_loss_grad: image pointer of view %d is null", v);
+      return GS_ERR_INVALID;
+    }
+    W[v] = cams[v].width;
+    H[v] = cams[v].height;
+  }
+  gs_status st = set_device(ctx);
+  if (st != GS_OK) return st;
+  return launch_loss(ctx, rendered, target, W, H, n_views, lambda_dssim, loss_out, dl_dimg,
+                     (hipStream_t)stream);
+}
+
+gs_status gs_render_bwd(gs_ctx* ctx, gs_frame* frame, gs_params params,
+                        const float* const* dl_dimg, gs_params grads, int32_t accumulate,
+                        void* stream) {
+  if (ctx == nullptr || frame == nullptr || dl_dimg == nullptr) {
+    set_error("gs_render_bwd: null argument");
+    return GS_ERR_INVALID;
+  }
+  if (frame->ctx != ctx) {
+    set_error("gs_render_bwd: frame belongs to another context");
+    return GS_ERR_INVALID;
+  }
+  if (!valid_params(params, "gs_render_bwd (params)") ||
+      !valid_params(grads, "gs_render_bwd (grads)"))
+    return GS_ERR_INVALID;
+  if (params.n != frame->n || grads.n != frame->n || params.sh_degree != frame->sh_degree ||
+      grads.sh_degree != frame->sh_degree) {
+    set_error("gs_render_bwd: parameter shapes differ from the frame's forward pass");
+    return GS_ERR_INVALID;
+  }
+  Frame& f = *frame;
+  for (int v = 0; v < f.views; ++v) {
+    if (dl_dimg[v] == nullptr) {
+      set_error("gs_render_bwd: dl_dimg[%d] is null", v);
+      return GS_ERR_INVALID;
+    }
+    f.vt.v[v].dimg = dl_dimg[v];
+  }
+  gs_status st = set_device(ctx);
+  if (st != GS_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  if (f.K > 0) {
+    st = launch_blend_bwd(f.vt, f, s);
+    if (st != GS_OK) return st;
+  }
+  GradsDev g;
+  g.means = grads.means;
+  g.log_scales = grads.log_scales;
+  g.quats = grads.quats;
+  g.logits = grads.opacity_logits;
+  g.sh = grads.sh;
+  g.accumulate = accumulate;
+  return launch_preprocess_bwd(params_dev(params), f.vt, f, g, s);
+}
+
+gs_status gs_adam_step(gs_ctx* ctx, gs_params p, gs_params g, gs_params m, gs_params v,
+                       const gs_adam_opts* opts, int64_t step, void* stream) {
+  if (ctx == nullptr || opts == nullptr) {
+    set_error("gs_adam_step: null argument");
+    return GS_ERR_INVALID;
+  }
+  if (!valid_params(p, "gs_adam_step (p)") || !valid_params(g, "gs_adam_step (g)") ||
+      !valid_params(m, "gs_adam_step (m)") || !valid_params(v, "gs_adam_step (v)"))
+    return GS_ERR_INVALID;
+  if (g.n != p.n || m.n != p.n || v.n != p.n || g.sh_degree != p.sh_degree ||
+      m.sh_degree != p.sh_degree || v.sh_degree != p.sh_degree) {
+    set_error("gs_adam_step: p, g, m, v shapes differ");
+    return GS_ERR_INVALID;
+  }
+  if (step < 1) {
+    set_error("gs_adam_step: step %lld < 1", (long long)step);
+    return GS_ERR_INVALID;
+  }
+  if (!(opts->beta1 >= 0.f && opts->beta1 < 1.f && opts->beta2 >= 0.f && opts->beta2 < 1.f)) {
+    set_error("gs_adam_step: betas must lie in [0, 1)");
+    return GS_ERR_INVALID;
+  }
+  gs_status st = set_device(ctx);
+  if (st != GS_OK) return st;
+  return launch_adam(p, g, m, v, *opts, step, (hipStream_t)stream);
+}
+
+gs_status gs_frame_stats_get(gs_frame* frame, gs_frame_stats* out) {
+  if (frame == nullptr || out == nullptr) {
+    set_error("gs_frame_stats_get: null argument");
+    return GS_ERR_INVALID;
+  }
+  out->n_views = frame->views;
+  out->tile = frame->tile;
+  out->n_gaussians = frame->n;
+  out->n_records = frame->K;
+  out->n_visible = frame->visible;
+  out->n_tiles = frame->vt.total_tiles;
+  out->n_pixels = frame->total_pix;
+  out->device_bytes = (int64_t)frame->bytes();
+  return GS_OK;
+}
+
+gs_status gs_frame_export(gs_frame* frame, int32_t what, int32_t view, void* dst, size_t bytes,
+                          void* stream) {
+  if (frame == nullptr || dst == nullptr) {
+    set_error("gs_frame_export: null argument");
+    return GS_ERR_INVALID;
+  }
+  Frame& f = *frame;
+  if (view < -1 || view >= f.views) {
+    set_error("gs_frame_export: view %d out of range", view);
+    return GS_ERR_INVALID;
+  }
+  gs_status st = set_device(f.ctx);
+  if (st != GS_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  const size_t n = (size_t)f.n;
+  size_t need = 0, off = 0;
+  const void* src = nullptr;
+  switch (what) {
+    case GS_EXPORT_KEYS:
+      need = (size_t)f.K * 8;
+      if (view != -1) break;
+      if (bytes < need) break;
+      return launch_export_keys(f, (uint64_t*)dst, s);
+    case GS_EXPORT_VALUES:
+      need = (size_t)f.K * 4;
+      src = f.tval[f.tkey_sel].p;
+      if (view != -1) need = 0;
+      break;
+    case GS_EXPORT_RANGES:
+      need = (size_t)f.vt.total_tiles * 8;
+      src = f.ranges.p;
+      if (view >= 0) {
+        const CamDev& c = f.vt.v[view];
+        off = (size_t)c.tile_offset * 8;
+        need = (size_t)c.tiles_x * c.tiles_y * 8;
+      }
+      break;
+    case GS_EXPORT_FINAL_T:
+    case GS_EXPORT_N_CONTRIB:
+      src = (what == GS_EXPORT_FINAL_T) ? f.finalT.p : f.ncon.p;
+      need = (size_t)f.total_pix * 4;
+      if (view >= 0) {
+        const CamDev& c = f.vt.v[view];
+        off = (size_t)c.pix_offset * 4;
+        need = (size_t)c.W * c.H * 4;
+      }
+      break;
+    case GS_EXPORT_SCREEN_GRADS:
+      src = f.acc.p;
+      need = (size_t)f.views * 9 * n * 4;
+      if (view >= 0) {
+        off = (size_t)view * 9 * n * 4;
+        need = 9 * n * 4;
+      }
+      break;
+    case GS_EXPORT_SPLATS:
+      src = f.splat.p;
+      need = (size_t)f.views * n * 48;
+      if (view >= 0) {
+        off = (size_t)view * n * 48;
+        need = n * 48;
+      }
+      break;
+    case GS_EXPORT_RECTS:
+      // stored packed as uint2; unpacked to 4 x u32 on the host side of the copy
+      src = f.rect.p;
+      need = (size_t)f.views * n * 8;
+      if (view >= 0) {
+        off = (size_t)view * n * 8;
+        need = n * 8;
+      }
+      break;
+    default:
+      set_error("gs_frame_export: unknown export %d", what);
+      return GS_ERR_INVALID;
+  }
+  if (src == nullptr || need == 0 || bytes < need) {
+    set_error("gs_frame_export: export %d of view %d needs %zu bytes (have %zu)", what, view, need,
+              bytes);
+    return GS_ERR_INVALID;
+  }
+  GS_HIP(hipMemcpyAsync(dst, (const char*)src + off, need, hipMemcpyDeviceToDevice, s));
+  return GS_OK;
+}
+
+void gs_frame_release(gs_frame* frame) {
+  if (frame == nullptr) return;
+  (void)hipSetDevice(frame->ctx->device);
+  (void)hipDeviceSynchronize();
+  frame_free(frame);
+  delete frame;
+}
+
+}  // extern "C"

@@ -1,0 +1,184 @@
+// Internal declarations of the isogs HIP library (gfx950 only).
+//
+// Data layout in HBM (per frame of V views over N Gaussians):
+//   splat   float4[V*N*3]  per (view, Gaussian): {A, B, C, opacity},
+//                          {int(floor(mx)), int(floor(my)), 0.5-frac(mx), 0.5-frac(my)},
+//                          {r, g, b, depth}
+//   rect    uint2[V*N]     tile rectangle, x0 | y0 << 16 and x1 | y1 << 16
+//   dkey    u32[V*N]       float32 depth bits, 0xffffffff when untouched
+//   clampm  u8[V*N]        SH clamp mask (bit c set: channel c clamped at 0)
+//   sidx    u32[V*N]       (view*N + gid) in (depth bits, index) order
+//   offs    u32[V*N]       exclusive scan of tiles touched, in sidx order
+//   tkey    u32[K]         global tile id of each record, tile-sorted
+//   tval    u32[K]         view*N + gid of each record
+//   ranges  uint2[tiles]   [start, end) per global tile
+//   finalT  f32[P], ncon u32[P]   per pixel over all views
+//   acc     f32[V][9][N]   screen-space gradient accumulators
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <string>
+
+#include "isogs.h"
+
+namespace isogs {
+
+constexpr int kMaxViews = 16;
+
+struct CamDev {
+  float R[9];
+  float t[3];
+  float fx, fy, cx, cy, znear;
+  float campos[3];
+  int W, H, tiles_x, tiles_y;
+  int tile_offset;  // first global tile id of the view
+  int reserved;
+  long long pix_offset;  // first pixel of the view in the frame-wide pixel arrays
+  float* image;          // forward output [3][H][W]
+  const float* dimg;     // upstream gradient [3][H][W]
+};
+
+struct ViewTable {
+  int n;            // number of views
+  int tile;         // tile side in pixels
+  int total_tiles;  // tiles over all views
+  int reserved;
+  float bg[3];
+  float reserved2;
+  CamDev v[kMaxViews];
+};
+
+struct ParamsDev {
+  const float* means;
+  const float* log_scales;
+  const float* quats;
+  const float* logits;
+  const float* sh;
+  int n;
+  int sh_degree;
+};
+
+struct GradsDev {
+  float* means;
+  float* log_scales;
+  float* quats;
+  float* logits;
+  float* sh;
+  int accumulate;
+};
+
+__host__ __device__ inline int view_of_tile(const ViewTable& vt, int gt) {
+  int v = 0;
+  for (int i = 1; i < vt.n; ++i)
+    if (gt >= vt.v[i].tile_offset) v = i;
+  return v;
+}
+
+// ----------------------------------------------------------------- errors
+void set_error(const char* fmt, ...);
+gs_status hip_fail(hipError_t e, const char* what);
+
+#define GS_HIP(call)                                    \
+  do {                                                  \
+    hipError_t e_ = (call);                             \
+    if (e_ != hipSuccess) return hip_fail(e_, #call);   \
+  } while (0)
+
+#define GS_LAUNCHED(name)                                        \
+  do {                                                           \
+    hipError_t e_ = hipGetLastError();                           \
+    if (e_ != hipSuccess) return hip_fail(e_, "launch " name);  \
+  } while (0)
+
+// ------------------------------------------------------------ device memory
+struct Ctx;
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t cap = 0;
+};
+
+gs_status buf_ensure(Ctx* ctx, DevBuf& b, size_t bytes);
+void buf_free(Ctx* ctx, DevBuf& b);
+
+struct Ctx {
+  int device = 0;
+  size_t budget = 0;
+  size_t in_use = 0;
+  size_t peak = 0;
+  int cu_count = 0;
+  hipDeviceProp_t prop;
+  void* loss_scratch = nullptr;  // loss.hip workspace (g maps, block partials)
+};
+
+void free_loss_scratch(Ctx* ctx);
+
+// Radix-sort / scan scratch.
+struct SortScratch {
+  DevBuf hist;      // u32[256 * blocks]
+  DevBuf partial;   // u64[blocks]
+  DevBuf total;     // u64[1]
+};
+
+struct Frame {
+  Ctx* ctx = nullptr;
+  int64_t n = 0;
+  int views = 0;
+  int tile = 16;
+  int depth = 256;
+  int sh_degree = 0;
+  ViewTable vt;
+  int64_t K = 0;
+  int64_t visible = 0;
+  int64_t total_pix = 0;
+  int key_bits = 1;
+  DevBuf splat, rect, dkey, dkw[2], sidx[2], clampm, offs, tkey[2], tval[2], ranges, finalT,
+      ncon, acc;
+  int tkey_sel = 0;  // which of tkey/tval holds the sorted records
+  int sidx_sel = 0;  // which of sidx holds the depth-sorted (view, Gaussian) indices
+  bool acc_zeroed = false;
+  SortScratch ss;
+  uint64_t* pinned = nullptr;  // host-pinned readback word
+  size_t bytes() const;
+};
+
+// ----------------------------------------------------------- kernel hosts
+// preprocess.hip
+gs_status launch_preprocess_fwd(const ParamsDev& p, const ViewTable& vt, Frame& f,
+                                hipStream_t s);
+gs_status launch_preprocess_bwd(const ParamsDev& p, const ViewTable& vt, Frame& f,
+                                const GradsDev& g, hipStream_t s);
+gs_status launch_init_points(const float* xyz, int64_t n, const gs_init_opts& o,
+                             uint64_t seed, gs_params out, hipStream_t s);
+// sort.hip
+// Stable LSD sort of n (key, value) pairs on key bits [0, bits): the first pass
+// reads kin/vin (vin == nullptr: values are the indices 0..n-1) and passes
+// alternate between buffer pairs A and B; *result_in_b tells where the result is.
+gs_status sort_pairs_u32(Ctx* ctx, SortScratch& ss, const uint32_t* kin, const uint32_t* vin,
+                         uint32_t* kA, uint32_t* vA, uint32_t* kB, uint32_t* vB, uint32_t n,
+                         const uint32_t* d_n, int bits, int* result_in_b, hipStream_t s);
+gs_status scan_tile_counts(Ctx* ctx, SortScratch& ss, const uint32_t* sidx, const uint2* rect,
+                           uint32_t n, uint32_t* offs, uint64_t* d_total, hipStream_t s);
+gs_status launch_emit(const ViewTable& vt, Frame& f, const uint32_t* sidx, uint32_t count,
+                      hipStream_t s);
+gs_status launch_ranges(Frame& f, hipStream_t s);
+gs_status launch_fill_u32(void* p, uint32_t value, size_t count, hipStream_t s);
+gs_status launch_export_keys(Frame& f, uint64_t* dst, hipStream_t s);
+// blend.hip
+gs_status launch_blend_fwd(const ViewTable& vt, Frame& f, hipStream_t s);
+gs_status launch_blend_bwd(const ViewTable& vt, Frame& f, hipStream_t s);
+// loss.hip
+gs_status launch_loss(Ctx* ctx, const float* const* x, const float* const* y, const int* W,
+                      const int* H, int nv, float lambda, float* loss_out, float* const* dl,
+                      hipStream_t s);
+// adam.hip
+gs_status launch_adam(const gs_params& p, const gs_params& g, const gs_params& m,
+                      const gs_params& v, const gs_adam_opts& o, int64_t step, hipStream_t s);
+
+}  // namespace isogs
+
+struct gs_ctx : isogs::Ctx {};
+struct gs_frame : isogs::Frame {};

@@ -1,0 +1,391 @@
+// Tile binning: exclusive scan of per-Gaussian tile counts, record emission,
+// a stable LSD radix sort of (u32 key, u32 value) pairs, and per-tile ranges.
+//
+// Order contract: records sorted by the 64-bit key (tile << 32) | depth bits,
+// ties by (view * N + Gaussian index).  The LSD sort of that key is split in
+// two: the 32 low (depth) digits are sorted once per (view, Gaussian) — every
+// record of a Gaussian shares its depth — and records are then emitted in that
+// order, so only the tile digits are sorted over the K records.  The result is
+// the same permutation an LSD sort of the full 64-bit key over the emitted
+// records gives, at a fraction of the traffic.
+//
+// Radix passes use 8-bit digits, 256 threads (4 waves of 64) and 16 keys per
+// thread per block.  Stable ranking inside a block uses wave ballots: for each
+// item slot the lanes holding the same digit are found with 8 ballots, the
+// group's leader bumps a per-wave LDS counter, and lanes take their rank from
+// the popcount of lower peer lanes.
+#include "internal.h"
+
+namespace isogs {
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kWaves = kThreads / 64;
+constexpr int kItems = 16;
+constexpr int kChunk = kThreads * kItems;  // 4096 elements per block
+constexpr int kRadix = 256;
+
+__device__ inline uint32_t load_n(uint32_t n_max, const uint32_t* d_n) {
+  if (d_n == nullptr) return n_max;
+  const uint32_t c = *d_n;
+  return c < n_max ? c : n_max;
+}
+
+__device__ inline uint64_t lanemask_lt() {
+  const int lane = __lane_id();
+  return (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
+}
+
+// ---------------------------------------------------------------- block scan
+// Exclusive scan of one u64 value per thread over a 256-thread block.
+__device__ inline uint64_t block_exclusive_scan(uint64_t x, uint64_t* sh_waves, uint64_t& total) {
+  const int lane = __lane_id();
+  const int wave = threadIdx.x / 64;
+  uint64_t inc = x;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint64_t y = __shfl_up(inc, d, 64);
+    if (lane >= d) inc += y;
+  }
+  if (lane == 63) sh_waves[wave] = inc;
+  __syncthreads();
+  uint64_t before = 0;
+  total = 0;
+  for (int w = 0; w < kWaves; ++w) {
+    const uint64_t s = sh_waves[w];
+    if (w < wave) before += s;
+    total += s;
+  }
+  __syncthreads();
+  return before + inc - x;
+}
+
+// Scan input: tile counts of (view, Gaussian) entries in sorted order.
+struct CountsIn {
+  const uint32_t* sidx;
+  const uint2* rect;
+  __device__ uint32_t operator()(uint32_t i) const {
+    const uint2 r = rect[sidx[i]];
+    const int x0 = (int)(r.x & 0xffffu), y0 = (int)(r.x >> 16);
+    const int x1 = (int)(r.y & 0xffffu), y1 = (int)(r.y >> 16);
+    if (x1 < x0 || y1 < y0) return 0u;
+    return (uint32_t)((x1 - x0 + 1) * (y1 - y0 + 1));
+  }
+};
+
+struct ArrayIn {
+  const uint32_t* a;
+  __device__ uint32_t operator()(uint32_t i) const { return a[i]; }
+};
+
+template <class F>
+__global__ __launch_bounds__(kThreads) void k_scan_reduce(F f, uint32_t n, uint64_t* partial) {
+  __shared__ uint64_t sw[kWaves];
+  const uint32_t base = blockIdx.x * (uint32_t)kChunk;
+  uint64_t s = 0;
+#pragma unroll 4
+  for (int j = 0; j < kItems; ++j) {
+    const uint32_t i = base + j * kThreads + threadIdx.x;
+    if (i < n) s += f(i);
+  }
+  uint64_t total;
+  block_exclusive_scan(s, sw, total);
+  if (threadIdx.x == 0) partial[blockIdx.x] = total;
+}
+
+// Single block: exclusive scan of the block partials in place; total to *d_total.
+__global__ __launch_bounds__(kThreads) void k_scan_partials(uint64_t* partial, uint32_t nb,
+                                                            uint64_t* d_total) {
+  __shared__ uint64_t sw[kWaves];
+  uint64_t carry = 0;
+  for (uint32_t base = 0; base < nb; base += kThreads) {
+    const uint32_t i = base + threadIdx.x;
+    const uint64_t x = (i < nb) ? partial[i] : 0ull;
+    uint64_t total;
+    const uint64_t ex = block_exclusive_scan(x, sw, total);
+    if (i < nb) partial[i] = carry + ex;
+    carry += total;
+  }
+  if (threadIdx.x == 0 && d_total != nullptr) *d_total = carry;
+}
+
+template <class F>
+__global__ __launch_bounds__(kThreads) void k_scan_down(F f, uint32_t n, const uint64_t* partial,
+                                                        uint32_t* out) {
+  __shared__ uint64_t sw[kWaves];
+  const uint32_t base = blockIdx.x * (uint32_t)kChunk;
+  // each thread owns kItems consecutive elements
+  const uint32_t first = base + threadIdx.x * kItems;
+  uint32_t v[kItems];
+  uint64_t s = 0;
+#pragma unroll
+  for (int j = 0; j < kItems; ++j) {
+    const uint32_t i = first + j;
+    v[j] = (i < n) ? f(i) : 0u;
+    s += v[j];
+  }
+  uint64_t total;
+  uint64_t run = block_exclusive_scan(s, sw, total) + partial[blockIdx.x];
+#pragma unroll
+  for (int j = 0; j < kItems; ++j) {
+    const uint32_t i = first + j;
+    if (i < n) out[i] = (uint32_t)run;
+    run += v[j];
+  }
+}
+
+// ---------------------------------------------------------------- radix sort
+__global__ __launch_bounds__(kThreads) void k_radix_hist(const uint32_t* __restrict__ keys,
+                                                         uint32_t n_max, const uint32_t* d_n,
+                                                         int shift, uint32_t nblocks,
+                                                         uint32_t* __restrict__ hist) {
+  __shared__ uint32_t h[kWaves][kRadix];
+  const int wave = threadIdx.x / 64, lane = __lane_id();
+  for (int d = threadIdx.x; d < kWaves * kRadix; d += kThreads) (&h[0][0])[d] = 0;
+  __syncthreads();
+  const uint32_t n = load_n(n_max, d_n);
+  const uint32_t base = blockIdx.x * (uint32_t)kChunk + wave * 64 * kItems;
+#pragma unroll 4
+  for (int j = 0; j < kItems; ++j) {
+    const uint32_t i = base + j * 64 + lane;
+    if (i < n) atomicAdd(&h[wave][(keys[i] >> shift) & 0xffu], 1u);
+  }
+  __syncthreads();
+  for (int d = threadIdx.x; d < kRadix; d += kThreads) {
+    uint32_t s = 0;
+    for (int w = 0; w < kWaves; ++w) s += h[w][d];
+    hist[(size_t)d * nblocks + blockIdx.x] = s;
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_radix_scatter(
+    const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin, uint32_t* __restrict__ kout,
+    uint32_t* __restrict__ vout, uint32_t n_max, const uint32_t* d_n, int shift, uint32_t nblocks,
+    const uint32_t* __restrict__ hist_scanned) {
+  __shared__ uint32_t cnt[kWaves][kRadix];
+  __shared__ uint32_t gofs[kRadix];
+  const int wave = threadIdx.x / 64, lane = __lane_id();
+  for (int d = threadIdx.x; d < kWaves * kRadix; d += kThreads) (&cnt[0][0])[d] = 0;
+  const uint32_t n = load_n(n_max, d_n);
+  const uint32_t base = blockIdx.x * (uint32_t)kChunk + wave * 64 * kItems;
+  if (blockIdx.x * (uint32_t)kChunk >= n) return;  // whole block empty (uniform)
+  uint32_t key[kItems], val[kItems], rank[kItems];
+#pragma unroll
+  for (int j = 0; j < kItems; ++j) {
+    const uint32_t i = base + j * 64 + lane;
+    const bool ok = i < n;
+    key[j] = ok ? kin[i] : 0u;
+    val[j] = ok ? (vin != nullptr ? vin[i] : i) : 0u;
+  }
+  __syncthreads();
+  const uint64_t lt = lanemask_lt();
+#pragma unroll
+  for (int j = 0; j < kItems; ++j) {
+    const uint32_t i = base + j * 64 + lane;
+    const bool ok = i < n;
+    const uint32_t d = (key[j] >> shift) & 0xffu;
+    uint64_t peers = __ballot(ok);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const uint64_t bb = __ballot((d >> b) & 1u);
+      peers &= ((d >> b) & 1u) ? bb : ~bb;
+    }
+    uint32_t old = 0;
+    const int leader = 63 - __clzll((long long)peers);
+    if (ok && lane == leader) {
+      old = cnt[wave][d];
+      cnt[wave][d] = old + (uint32_t)__popcll(peers);
+    }
+    old = __shfl(old, ok ? leader : lane, 64);
+    rank[j] = old + (uint32_t)__popcll(peers & lt);
+  }
+  __syncthreads();
+  for (int d = threadIdx.x; d < kRadix; d += kThreads) {
+    uint32_t run = 0;
+    for (int w = 0; w < kWaves; ++w) {
+      const uint32_t c = cnt[w][d];
+      cnt[w][d] = run;
+      run += c;
+    }
+    gofs[d] = hist_scanned[(size_t)d * nblocks + blockIdx.x];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < kItems; ++j) {
+    const uint32_t i = base + j * 64 + lane;
+    if (i < n) {
+      const uint32_t d = (key[j] >> shift) & 0xffu;
+      const uint32_t pos = gofs[d] + cnt[wave][d] + rank[j];
+      kout[pos] = key[j];
+      vout[pos] = val[j];
+    }
+  }
+}
+
+// ---------------------------------------------------------------- emission
+__global__ __launch_bounds__(256) void k_emit(ViewTable vt, int n_gauss,
+                                              const uint32_t* __restrict__ sidx,
+                                              const uint2* __restrict__ rect,
+                                              const uint32_t* __restrict__ offs, uint32_t count,
+                                              uint32_t cap, uint32_t* __restrict__ tkey,
+                                              uint32_t* __restrict__ tval,
+                                              uint32_t* overflow) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const uint32_t idx = sidx[i];
+  const uint2 r = rect[idx];
+  const int x0 = (int)(r.x & 0xffffu), y0 = (int)(r.x >> 16);
+  const int x1 = (int)(r.y & 0xffffu), y1 = (int)(r.y >> 16);
+  if (x1 < x0 || y1 < y0) return;
+  const int v = (int)(idx / (uint32_t)n_gauss);
+  const int tx = vt.v[v].tiles_x, toff = vt.v[v].tile_offset;
+  uint32_t o = offs[i];
+  const uint32_t need = (uint32_t)((x1 - x0 + 1) * (y1 - y0 + 1));
+  if ((uint64_t)o + need > cap) {
+    if (overflow != nullptr) *overflow = 1u;
+    return;
+  }
+  for (int y = y0; y <= y1; ++y)
+    for (int x = x0; x <= x1; ++x) {
+      tkey[o] = (uint32_t)(toff + y * tx + x);
+      tval[o] = idx;
+      ++o;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ tkey, uint32_t K_max,
+                                                const uint32_t* d_K, uint2* __restrict__ ranges) {
+  const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t K = load_n(K_max, d_K);
+  if (k >= K) return;
+  const uint32_t t = tkey[k];
+  if (k == 0 || tkey[k - 1] != t) ranges[t].x = k;
+  if (k == K - 1 || tkey[k + 1] != t) ranges[t].y = k + 1;
+}
+
+__global__ __launch_bounds__(256) void k_fill_u32(uint32_t* p, uint32_t value, size_t count) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < count;
+       i += (size_t)gridDim.x * blockDim.x)
+    p[i] = value;
+}
+
+__global__ __launch_bounds__(256) void k_export_keys(const uint32_t* __restrict__ tkey,
+                                                     const uint32_t* __restrict__ tval,
+                                                     const uint32_t* __restrict__ dkey, uint32_t K,
+                                                     uint64_t* __restrict__ out) {
+  const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= K) return;
+  out[k] = ((uint64_t)tkey[k] << 32) | (uint64_t)dkey[tval[k]];
+}
+
+inline uint32_t nblocks_of(uint32_t n) { return (n + kChunk - 1) / kChunk; }
+
+}  // namespace
+
+gs_status launch_fill_u32(void* p, uint32_t value, size_t count, hipStream_t s) {
+  if (count == 0) return GS_OK;
+  size_t blocks = (count + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks), dim3(256), 0, s, (uint32_t*)p, value,
+                     count);
+  GS_LAUNCHED("fill_u32");
+  return GS_OK;
+}
+
+static gs_status ensure_scratch(Ctx* ctx, SortScratch& ss, uint32_t nb, size_t hist_entries) {
+  gs_status st = buf_ensure(ctx, ss.partial, sizeof(uint64_t) * (size_t)(nb + 1));
+  if (st != GS_OK) return st;
+  st = buf_ensure(ctx, ss.total, sizeof(uint64_t) * 2);
+  if (st != GS_OK) return st;
+  return buf_ensure(ctx, ss.hist, sizeof(uint32_t) * (hist_entries + 1));
+}
+
+gs_status scan_tile_counts(Ctx* ctx, SortScratch& ss, const uint32_t* sidx, const uint2* rect,
+                           uint32_t n, uint32_t* offs, uint64_t* d_total, hipStream_t s) {
+  const uint32_t nb = nblocks_of(n);
+  gs_status st = ensure_scratch(ctx, ss, nb, 0);
+  if (st != GS_OK) return st;
+  CountsIn f{sidx, rect};
+  auto* partial = (uint64_t*)ss.partial.p;
+  hipLaunchKernelGGL(k_scan_reduce<CountsIn>, dim3(nb), dim3(kThreads), 0, s, f, n, partial);
+  GS_LAUNCHED("scan_reduce");
+  hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kThreads), 0, s, partial, nb, d_total);
+  GS_LAUNCHED("scan_partials");
+  hipLaunchKernelGGL(k_scan_down<CountsIn>, dim3(nb), dim3(kThreads), 0, s, f, n, partial, offs);
+  GS_LAUNCHED("scan_down");
+  return GS_OK;
+}
+
+gs_status sort_pairs_u32(Ctx* ctx, SortScratch& ss, const uint32_t* kin, const uint32_t* vin,
+                         uint32_t* kA, uint32_t* vA, uint32_t* kB, uint32_t* vB, uint32_t n,
+                         const uint32_t* d_n, int bits, int* result_in_b, hipStream_t s) {
+  *result_in_b = 0;
+  if (n == 0) return GS_OK;
+  const uint32_t nb = nblocks_of(n);
+  const uint32_t hist_n = (uint32_t)kRadix * nb;
+  const uint32_t hb = nblocks_of(hist_n);
+  gs_status st = ensure_scratch(ctx, ss, hb > nb ? hb : nb, hist_n);
+  if (st != GS_OK) return st;
+  auto* hist = (uint32_t*)ss.hist.p;
+  auto* partial = (uint64_t*)ss.partial.p;
+  uint32_t* kb[2] = {kA, kB};
+  uint32_t* vb[2] = {vA, vB};
+  const uint32_t* ki = kin;
+  const uint32_t* vi = vin;
+  int out = 0;
+  for (int shift = 0; shift < bits; shift += 8) {
+    hipLaunchKernelGGL(k_radix_hist, dim3(nb), dim3(kThreads), 0, s, ki, n, d_n, shift, nb, hist);
+    GS_LAUNCHED("radix_hist");
+    ArrayIn f{hist};
+    hipLaunchKernelGGL(k_scan_reduce<ArrayIn>, dim3(hb), dim3(kThreads), 0, s, f, hist_n, partial);
+    GS_LAUNCHED("radix_scan_reduce");
+    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kThreads), 0, s, partial, hb,
+                       (uint64_t*)nullptr);
+    GS_LAUNCHED("radix_scan_partials");
+    hipLaunchKernelGGL(k_scan_down<ArrayIn>, dim3(hb), dim3(kThreads), 0, s, f, hist_n, partial,
+                       hist);
+    GS_LAUNCHED("radix_scan_down");
+    hipLaunchKernelGGL(k_radix_scatter, dim3(nb), dim3(kThreads), 0, s, ki, vi, kb[out], vb[out],
+                       n, d_n, shift, nb, hist);
+    GS_LAUNCHED("radix_scatter");
+    ki = kb[out];
+    vi = vb[out];
+    *result_in_b = out;
+    out ^= 1;
+  }
+  return GS_OK;
+}
+
+gs_status launch_emit(const ViewTable& vt, Frame& f, const uint32_t* sidx, uint32_t count,
+                      hipStream_t s) {
+  if (count == 0) return GS_OK;
+  const size_t cap_bytes = f.tkey[0].cap < f.tval[0].cap ? f.tkey[0].cap : f.tval[0].cap;
+  const uint32_t cap = (uint32_t)(cap_bytes / sizeof(uint32_t));
+  hipLaunchKernelGGL(k_emit, dim3((count + 255) / 256), dim3(256), 0, s, vt, (int)f.n, sidx,
+                     (const uint2*)f.rect.p, (const uint32_t*)f.offs.p, count, cap,
+                     (uint32_t*)f.tkey[0].p, (uint32_t*)f.tval[0].p, (uint32_t*)nullptr);
+  GS_LAUNCHED("emit");
+  return GS_OK;
+}
+
+gs_status launch_ranges(Frame& f, hipStream_t s) {
+  gs_status st = launch_fill_u32(f.ranges.p, 0u, (size_t)f.vt.total_tiles * 2, s);
+  if (st != GS_OK) return st;
+  if (f.K == 0) return GS_OK;
+  hipLaunchKernelGGL(k_ranges, dim3((unsigned)((f.K + 255) / 256)), dim3(256), 0, s,
+                     (const uint32_t*)f.tkey[f.tkey_sel].p, (uint32_t)f.K,
+                     (const uint32_t*)nullptr, (uint2*)f.ranges.p);
+  GS_LAUNCHED("ranges");
+  return GS_OK;
+}
+
+gs_status launch_export_keys(Frame& f, uint64_t* dst, hipStream_t s) {
+  if (f.K == 0) return GS_OK;
+  hipLaunchKernelGGL(k_export_keys, dim3((unsigned)((f.K + 255) / 256)), dim3(256), 0, s,
+                     (const uint32_t*)f.tkey[f.tkey_sel].p, (const uint32_t*)f.tval[f.tkey_sel].p,
+                     (const uint32_t*)f.dkey.p, (uint32_t)f.K, dst);
+  GS_LAUNCHED("export_keys");
+  return GS_OK;
+}
+
+}  // namespace isogs

@@ -1,0 +1,298 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Bars: tile keys, values (sort order) and ranges bit-exact; images within
+1e-4 max abs per channel (flagged threshold pixels accepted on either
+branch); gradients within 1e-3 relative L2 of the oracle.
+"""
+import numpy as np
+import pytest
+import torch
+
+import gsscenes
+from oracle import camera as ocam
+from oracle import loss as oloss
+from oracle import pipeline
+from tests._parity import assert_image, image_report, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+GROUPS = ("means", "log_scales", "quats", "opacity_logits", "sh")
+
+
+@pytest.fixture(scope="module")
+def P():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    import paper_2509_05216_amd as P
+    return P
+
+
+@pytest.fixture(scope="module")
+def ctx(P):
+    return P.Context(0)
+
+
+def _cams(n, W, H):
+    return [ocam.to_float32(c) for c in ocam.orbit_cameras(n, 2.5, 60.0, W, H)]
+
+
+def _oracle_fw(params, cams, tile, bg=(0.0, 0.0, 0.0)):
+    fws, off = [], 0
+    for c in cams:
+        f = pipeline.forward_view(params, c, tile, bg, tile_offset=off)
+        off += f["tiles"][0] * f["tiles"][1]
+        fws.append(f)
+    return fws
+
+
+def _check_binning(P, frame, fws, n):
+    keys = frame.export("keys").cpu().numpy().view(np.uint64)
+    vals = frame.export("values").cpu().numpy().view(np.uint32).astype(np.int64)
+    ranges = frame.export("ranges").cpu().numpy().view(np.uint32).reshape(-1, 2).astype(np.int64)
+    ok_keys = np.concatenate([f["lists"][0] for f in fws])
+    ok_vals = np.concatenate([v * n + f["lists"][1] for v, f in enumerate(fws)])
+    assert keys.shape == ok_keys.shape, (keys.shape, ok_keys.shape)
+    assert np.array_equal(keys, ok_keys)
+    assert np.array_equal(vals, ok_vals)
+    base, t0 = 0, 0
+    for f in fws:
+        r = f["lists"][2]
+        want = np.where(r[:, 1:2] > r[:, 0:1], r + base, 0)
+        assert np.array_equal(ranges[t0:t0 + r.shape[0]], want)
+        base += f["lists"][0].size
+        t0 += r.shape[0]
+
+
+# ------------------------------------------------------------------ forward
+@pytest.fixture(scope="module")
+def tiny(P):
+    scene = gsscenes.make_scene("tiny")
+    cams = _cams(8, 256, 256)
+    return scene, cams
+
+
+def test_tiny_forward_binning_and_image(P, ctx, tiny):
+    scene, cams = tiny
+    params = P.Params.from_numpy(scene.params)
+    sel = cams[:4]
+    imgs, frame = P.render_fwd(ctx, params, [P.camera_from_dict(c) for c in sel], tile=16)
+    torch.cuda.synchronize()
+    fws = _oracle_fw(scene.params, sel, 16)
+    _check_binning(P, frame, fws, scene.params["means"].shape[1])
+    T = frame.export("final_T").cpu().numpy()
+    nc = frame.export("n_contrib").cpu().numpy()
+    off = 0
+    for v, f in enumerate(fws):
+        r = assert_image(f, imgs[v].cpu().numpy())
+        print(f"view {v}: max err {r['max_err']:.2e}, flagged {r['n_flagged']}, "
+              f"rescued {r['rescued']}")
+        Tv = T[off:off + 256 * 256].reshape(256, 256)
+        nv = nc[off:off + 256 * 256].reshape(256, 256)
+        ok = ~r["flagged_mask"]
+        assert np.abs(Tv - f["T"])[ok].max() < 1e-5
+        assert np.array_equal(nv[ok], f["n"][ok])
+        off += 256 * 256
+
+
+@pytest.mark.parametrize("tile,depth", [(8, 32), (8, 64), (16, 64), (32, 32), (32, 256)])
+def test_ragged_views_tiles_and_depths(P, ctx, tile, depth):
+    scene = gsscenes.make_scene("tiny", n=3000)
+    sizes = [(200, 136), (96, 80), (257, 31)]
+    cams = [_cams(5, W, H)[i] for i, (W, H) in enumerate(sizes)]
+    params = P.Params.from_numpy(scene.params)
+    bg = (0.1, 0.2, 0.3)
+    imgs, frame = P.render_fwd(ctx, params, [P.camera_from_dict(c) for c in cams], tile=tile,
+                               lds_depth=depth, bg=bg)
+    torch.cuda.synchronize()
+    fws = _oracle_fw(scene.params, cams, tile, bg)
+    _check_binning(P, frame, fws, 3000)
+    for v, f in enumerate(fws):
+        assert_image(f, imgs[v].cpu().numpy(), bg=bg)
+
+
+def test_sh3_anisotropic_forward(P, ctx):
+    scene = gsscenes.make_scene("iso1m", n=4000, G=96)
+    cams = _cams(3, 192, 160)
+    params = P.Params.from_numpy(scene.params)
+    imgs, frame = P.render_fwd(ctx, params, [P.camera_from_dict(c) for c in cams])
+    torch.cuda.synchronize()
+    fws = _oracle_fw(scene.params, cams, 16)
+    _check_binning(P, frame, fws, 4000)
+    for v, f in enumerate(fws):
+        assert_image(f, imgs[v].cpu().numpy())
+
+
+def test_empty_and_single(P, ctx):
+    from tests._util import make_params
+    cams = _cams(2, 64, 48)
+    # everything behind the camera -> zero records, background image
+    p = make_params([[0, 0, 0]])
+    c = dict(cams[0])
+    c["t"] = np.array([0.0, 0.0, -5.0])
+    imgs, frame = P.render_fwd(ctx, P.Params.from_numpy(p), [P.camera_from_dict(c)],
+                               bg=(0.25, 0.5, 0.75))
+    torch.cuda.synchronize()
+    assert frame.stats()["n_records"] == 0
+    assert np.allclose(imgs[0].cpu().numpy(), np.array([0.25, 0.5, 0.75])[:, None, None])
+    # one Gaussian at the origin
+    p = make_params([[0.0, 0.0, 0.0]], log_scales=np.full(3, np.log(0.1)), logits=[2.0],
+                    sh=[[0.5], [0.2], [-0.1]])
+    imgs, frame = P.render_fwd(ctx, P.Params.from_numpy(p), [P.camera_from_dict(cams[1])])
+    torch.cuda.synchronize()
+    fws = _oracle_fw(p, [cams[1]], 16)
+    _check_binning(P, frame, fws, 1)
+    assert_image(fws[0], imgs[0].cpu().numpy())
+
+
+# ------------------------------------------------------------------ backward
+def test_backward_matches_oracle(P, ctx):
+    scene = gsscenes.make_scene("iso1m", n=3000, G=96)
+    cams = _cams(4, 160, 128)[:2]
+    params = P.Params.from_numpy(scene.params)
+    rng = np.random.default_rng(5)
+    ws = [rng.normal(size=(3, 128, 160)) for _ in cams]
+    imgs, frame = P.render_fwd(ctx, params, [P.camera_from_dict(c) for c in cams])
+    dl = [torch.tensor(w, dtype=torch.float32, device="cuda") for w in ws]
+    grads = P.render_bwd(ctx, frame, params, dl)
+    torch.cuda.synchronize()
+    # the screen accumulators are cleared by the backward; re-run the blend
+    # backward alone through a fresh forward to read them is not needed: compare params
+    fws = _oracle_fw(scene.params, cams, 16)
+    total = None
+    for c, f, w in zip(cams, fws, ws):
+        acc, g = pipeline.backward_view(scene.params, c, f, w)
+        total = pipeline.add_grads(total, g)
+    gg = grads.to_numpy()
+    for k in GROUPS:
+        e = rel_l2(gg[k], total[k])
+        print(f"{k}: rel L2 {e:.2e}")
+        assert e < 1e-3, (k, e)
+
+
+def test_screen_space_accumulators(P, ctx):
+    """dL/d(mean2D, conic, opacity, rgb) per Gaussian (the blend backward alone)."""
+    scene = gsscenes.make_scene("tiny", n=2000)
+    cams = _cams(3, 128, 128)[:1]
+    params = P.Params.from_numpy(scene.params)
+    w = np.random.default_rng(6).normal(size=(3, 128, 128))
+    imgs, frame = P.render_fwd(ctx, params, [P.camera_from_dict(c) for c in cams])
+    dl = [torch.tensor(w, dtype=torch.float32, device="cuda")]
+    grads = P.render_bwd(ctx, frame, params, dl)
+    torch.cuda.synchronize()
+    # after the pass the library clears its accumulators
+    acc_after = frame.export("screen_grads").cpu().numpy()
+    assert np.all(acc_after == 0)
+    f = _oracle_fw(scene.params, cams, 16)[0]
+    acc, g = pipeline.backward_view(scene.params, cams[0], f, w)
+    gg = grads.to_numpy()
+    for k in GROUPS:
+        assert rel_l2(gg[k], g[k]) < 1e-3, k
+
+
+# ------------------------------------------------------------------ loss, adam
+def test_loss_and_gradient(P, ctx):
+    rng = np.random.default_rng(9)
+    sizes = [(64, 48), (37, 29)]
+    xs = [rng.random((3, H, W)) for W, H in sizes]
+    ys = [np.clip(x + rng.normal(0, 0.1, x.shape), 0, 1) for x in xs]
+    cams = [P.camera(np.eye(3), [0, 0, 0], 50, 50, W / 2, H / 2, W, H) for W, H in sizes]
+    tx = [torch.tensor(x, dtype=torch.float32, device="cuda") for x in xs]
+    ty = [torch.tensor(y, dtype=torch.float32, device="cuda") for y in ys]
+    loss, grads = P.loss_grad(ctx, tx, ty, cams, 0.2)
+    torch.cuda.synchronize()
+    xs32 = [x.astype(np.float32).astype(np.float64) for x in xs]
+    ys32 = [y.astype(np.float32).astype(np.float64) for y in ys]
+    L, dl = oloss.batch_loss(xs32, ys32, 0.2)
+    assert abs(loss.item() - L) < 1e-5 * max(1, abs(L))
+    for g, d in zip(grads, dl):
+        assert rel_l2(g.cpu().numpy(), d) < 1e-4
+
+
+def test_adam_matches_oracle(P, ctx):
+    rng = np.random.default_rng(10)
+    n = 1001
+    mk = lambda: {"means": rng.normal(size=(3, n)), "log_scales": rng.normal(size=(3, n)),
+                  "quats": rng.normal(size=(4, n)), "opacity_logits": rng.normal(size=n),
+                  "sh": rng.normal(size=(48, n)), "sh_degree": 3}
+    p, g, m = mk(), mk(), mk()
+    v = {k: (np.abs(x) if isinstance(x, np.ndarray) else x) for k, x in mk().items()}
+    tp, tg, tm, tv = (P.Params.from_numpy(d) for d in (p, g, m, v))
+    P.adam_step(ctx, tp, tg, tm, tv, 7)
+    torch.cuda.synchronize()
+    f32 = lambda d: {k: (x.astype(np.float32).astype(np.float64) if isinstance(x, np.ndarray)
+                         else x) for k, x in d.items()}
+    np_, nm, nv = pipeline.adam_all(f32(p), f32(g), f32(m), f32(v), 7)
+    out = tp.to_numpy()
+    for k in GROUPS:
+        assert np.allclose(out[k], np_[k], rtol=1e-5, atol=1e-6), k
+        assert np.allclose(tm.to_numpy()[k], nm[k], rtol=1e-5, atol=1e-6), k
+
+
+# ------------------------------------------------------------------ full step
+def test_tiny_training_step(P, ctx, tiny):
+    """The tiny workload: 10k Gaussians, 8 orbit views at 256^2, one step."""
+    scene, cams = tiny
+    targets = [gsscenes.raycast(scene.field, c["R"], c["t"], c["fx"], c["fy"], c["cx"], c["cy"],
+                                256, 256, step=scene.h / 2) for c in cams]
+    params = P.Params.from_numpy(scene.params)
+    gc = [P.camera_from_dict(c) for c in cams]
+    imgs, frame = P.render_fwd(ctx, params, gc)
+    tt = [torch.tensor(t, device="cuda") for t in targets]
+    loss, dl = P.loss_grad(ctx, imgs, tt, gc)
+    grads = P.render_bwd(ctx, frame, params, dl)
+    torch.cuda.synchronize()
+    L, g, fws, dimgs, accs = pipeline.train_step_grads(scene.params, cams, targets)
+    for v, f in enumerate(fws):
+        assert_image(f, imgs[v].cpu().numpy())
+    assert abs(loss.item() - L) < 1e-4
+    gg = grads.to_numpy()
+    for k in GROUPS:
+        if np.linalg.norm(g[k]) == 0:
+            assert np.abs(gg[k]).max() < 1e-9, k
+            continue
+        e = rel_l2(gg[k], g[k])
+        print(f"{k}: rel L2 {e:.2e}")
+        assert e < 1e-3, (k, e)
+    m = params.zeros_like()
+    vv = params.zeros_like()
+    P.adam_step(ctx, params, grads, m, vv, 1)
+    torch.cuda.synchronize()
+    zeros = {k: np.zeros_like(x) for k, x in g.items()}
+    newp, _, _ = pipeline.adam_all(scene.params, g, zeros, zeros, 1)
+    out = params.to_numpy()
+    for k in GROUPS:
+        # first Adam step moves by lr * sign(g) wherever |g| >> eps
+        big = np.abs(g[k]) > 1e-8
+        assert np.allclose(out[k][big], newp[k][big], atol=1e-6), k
+
+
+def test_init_from_points_matches_oracle(P, ctx):
+    from oracle import init as oinit
+    rng = np.random.default_rng(11)
+    xyz = rng.uniform(-1, 1, (3, 5000)).astype(np.float32)
+    txyz = torch.tensor(xyz, device="cuda")
+    for kw in (dict(log_scale=-4.0, log_scale_jitter=0.5, random_quats=True, sh_std=0.1),
+               dict(log_scale_range=(-5.0, -3.0), random_quats=False, sh_std=0.0)):
+        p = P.init_from_points(ctx, txyz, 3, opacity_logit=0.1, seed=2024, **kw)
+        torch.cuda.synchronize()
+        o = oinit.init_from_points(xyz.astype(np.float64), 3, opacity_logit=0.1, seed=2024, **kw)
+        out = p.to_numpy()
+        assert np.array_equal(out["means"], xyz)
+        for k in ("log_scales", "quats", "sh"):
+            assert np.allclose(out[k], o[k], atol=2e-5), k
+        assert np.allclose(out["opacity_logits"], o["opacity_logits"])
+
+
+def test_autograd_function_matches_render_bwd(P, ctx):
+    scene = gsscenes.make_scene("tiny", n=1500)
+    cams = [P.camera_from_dict(c) for c in _cams(2, 96, 96)]
+    params = P.Params.from_numpy(scene.params)
+    ts = [t.clone().requires_grad_(True) for t in params.tensors()]
+    out = P.rasterize(ctx, ts, 0, cams)
+    w = torch.randn_like(out)
+    (out * w).sum().backward()
+    imgs, frame = P.render_fwd(ctx, params, cams)
+    g = P.render_bwd(ctx, frame, params, [w[0].contiguous(), w[1].contiguous()])
+    torch.cuda.synchronize()
+    for t, r in zip(ts, g.tensors()):
+        assert torch.allclose(t.grad, r, rtol=1e-5, atol=1e-7)

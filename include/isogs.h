@@ -155,6 +155,18 @@ void gs_ctx_destroy(gs_ctx* ctx);
 /* Bytes of device scratch currently held by the context and its frames. */
 gs_status gs_ctx_memory(gs_ctx* ctx, size_t* in_use, size_t* peak);
 
+/* Stage timing.  When enabled, every pipeline stage the context launches is
+ * bracketed by HIP events on its stream (the events add no work to the
+ * kernels).  Enabling or disabling resets the totals.  gs_ctx_stage_time
+ * waits for the recorded events and returns the summed duration (ms) and the
+ * number of timed launches of one stage; gs_stage_name gives the stage's name
+ * ("project", "depth_sort", "scan", "emit", "tile_sort", "ranges",
+ * "blend_fwd", "loss", "blend_bwd", "project_bwd", "adam", "init") or NULL
+ * past the last stage. */
+gs_status gs_ctx_set_timing(gs_ctx* ctx, int32_t enable);
+gs_status gs_ctx_stage_time(gs_ctx* ctx, int32_t stage, double* total_ms, int64_t* launches);
+const char* gs_stage_name(int32_t stage);
+
 /* Structured orbit of look-at views (Sec. III: synthetic views "in a
  * structured orbit"; Sec. IV: 448 views per dataset).  View i of n sits on a
  * Fibonacci sphere of the given radius at height y = 1 - 2 (i + 0.5) / n and

@@ -75,6 +75,10 @@ SIGNATURES = [
     ("gs_ctx_create", C.c_int, [C.c_int, C.c_size_t, C.POINTER(_P)]),
     ("gs_ctx_destroy", None, [_P]),
     ("gs_ctx_memory", C.c_int, [_P, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]),
+    ("gs_ctx_set_timing", C.c_int, [_P, C.c_int32]),
+    ("gs_ctx_stage_time", C.c_int, [_P, C.c_int32, C.POINTER(C.c_double),
+                                    C.POINTER(C.c_int64)]),
+    ("gs_stage_name", C.c_char_p, [C.c_int32]),
     ("gs_orbit_cameras", C.c_int, [C.c_int32, C.c_float, C.c_float, C.c_int32, C.c_int32,
                                    C.POINTER(GsCamera)]),
     ("gs_init_from_points", C.c_int, [_P, _P, C.c_int64, C.POINTER(GsInitOpts), C.c_uint64,

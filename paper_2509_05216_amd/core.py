@@ -39,6 +39,24 @@ class Context:
         L.check(L.lib().gs_ctx_memory(self.handle, C.byref(a), C.byref(b)))
         return a.value, b.value
 
+    def set_timing(self, enable=True):
+        """Bracket every stage with HIP events (resets the totals)."""
+        L.check(L.lib().gs_ctx_set_timing(self.handle, 1 if enable else 0))
+
+    def stage_times(self):
+        """{stage name: (total ms, launches)} of the timed stages."""
+        out = {}
+        i = 0
+        while True:
+            name = L.lib().gs_stage_name(i)
+            if name is None:
+                break
+            ms, cnt = C.c_double(), C.c_int64()
+            L.check(L.lib().gs_ctx_stage_time(self.handle, i, C.byref(ms), C.byref(cnt)))
+            out[name.decode()] = (ms.value, cnt.value)
+            i += 1
+        return out
+
     def close(self):
         if getattr(self, "handle", None):
             L.lib().gs_ctx_destroy(self.handle)

@@ -60,6 +60,74 @@ void buf_free(Ctx* ctx, DevBuf& b) {
   b.cap = 0;
 }
 
+// ------------------------------------------------------------ stage timing
+static hipEvent_t take_event(Ctx* c) {
+  if (c->n_free > 0) return c->free_events[--c->n_free];
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+static void give_event(Ctx* c, hipEvent_t e) {
+  if (e == nullptr) return;
+  if (c->n_free == c->cap_free) {
+    const int nc = c->cap_free ? 2 * c->cap_free : 64;
+    auto* p = new hipEvent_t[nc];
+    for (int i = 0; i < c->n_free; ++i) p[i] = c->free_events[i];
+    delete[] c->free_events;
+    c->free_events = p;
+    c->cap_free = nc;
+  }
+  c->free_events[c->n_free++] = e;
+}
+
+StageTimer::StageTimer(Ctx* c_, int st, hipStream_t s_) : c(c_), stage(st), s(s_) {
+  if (c == nullptr || !c->timing) return;
+  a = take_event(c);
+  if (a != nullptr && hipEventRecord(a, s) != hipSuccess) {
+    give_event(c, a);
+    a = nullptr;
+  }
+}
+
+StageTimer::~StageTimer() {
+  if (a == nullptr) return;
+  hipEvent_t b = take_event(c);
+  if (b == nullptr || hipEventRecord(b, s) != hipSuccess) {
+    give_event(c, a);
+    give_event(c, b);
+    return;
+  }
+  if (c->n_pending == c->cap_pending) {
+    const int nc = c->cap_pending ? 2 * c->cap_pending : 64;
+    auto* p = new PendingTiming[nc];
+    for (int i = 0; i < c->n_pending; ++i) p[i] = c->pending[i];
+    delete[] c->pending;
+    c->pending = p;
+    c->cap_pending = nc;
+  }
+  c->pending[c->n_pending++] = PendingTiming{stage, a, b};
+}
+
+gs_status timing_collect(Ctx* c) {
+  for (int i = 0; i < c->n_pending; ++i) {
+    PendingTiming& t = c->pending[i];
+    GS_HIP(hipEventSynchronize(t.b));
+    float ms = 0.f;
+    GS_HIP(hipEventElapsedTime(&ms, t.a, t.b));
+    c->stage_ms[t.stage] += ms;
+    c->stage_count[t.stage] += 1;
+    give_event(c, t.a);
+    give_event(c, t.b);
+  }
+  c->n_pending = 0;
+  return GS_OK;
+}
+
+static const char* kStageNames[ST_COUNT] = {
+    "project", "depth_sort", "scan", "emit", "tile_sort", "ranges", "blend_fwd",
+    "loss", "blend_bwd", "project_bwd", "adam", "init"};
+
 size_t Frame::bytes() const {
   size_t s = splat.cap + rect.cap + dkey.cap + dkw[0].cap + dkw[1].cap + sidx[0].cap +
              sidx[1].cap + clampm.cap + offs.cap + tkey[0].cap + tkey[1].cap + tval[0].cap +
@@ -252,7 +320,46 @@ void gs_ctx_destroy(gs_ctx* ctx) {
   (void)hipSetDevice(ctx->device);
   (void)hipDeviceSynchronize();
   free_loss_scratch(ctx);
+  (void)timing_collect(ctx);
+  for (int i = 0; i < ctx->n_free; ++i) (void)hipEventDestroy(ctx->free_events[i]);
+  delete[] ctx->free_events;
+  delete[] ctx->pending;
   delete ctx;
+}
+
+gs_status gs_ctx_set_timing(gs_ctx* ctx, int32_t enable) {
+  if (ctx == nullptr) {
+    set_error("gs_ctx_set_timing: null context");
+    return GS_ERR_INVALID;
+  }
+  gs_status st = set_device(ctx);
+  if (st != GS_OK) return st;
+  st = timing_collect(ctx);
+  if (st != GS_OK) return st;
+  ctx->timing = enable != 0;
+  for (int i = 0; i < ST_COUNT; ++i) {
+    ctx->stage_ms[i] = 0.0;
+    ctx->stage_count[i] = 0;
+  }
+  return GS_OK;
+}
+
+gs_status gs_ctx_stage_time(gs_ctx* ctx, int32_t stage, double* total_ms, int64_t* launches) {
+  if (ctx == nullptr || stage < 0 || stage >= ST_COUNT) {
+    set_error("gs_ctx_stage_time: bad context or stage %d", stage);
+    return GS_ERR_INVALID;
+  }
+  gs_status st = set_device(ctx);
+  if (st != GS_OK) return st;
+  st = timing_collect(ctx);
+  if (st != GS_OK) return st;
+  if (total_ms) *total_ms = ctx->stage_ms[stage];
+  if (launches) *launches = ctx->stage_count[stage];
+  return GS_OK;
+}
+
+const char* gs_stage_name(int32_t stage) {
+  return (stage >= 0 && stage < ST_COUNT) ? kStageNames[stage] : nullptr;
 }
 
 gs_status gs_ctx_memory(gs_ctx* ctx, size_t* in_use, size_t* peak) {
@@ -322,6 +429,7 @@ gs_status gs_init_from_points(gs_ctx* ctx, const float* xyz, int64_t n, const gs
   }
   gs_status st = set_device(ctx);
   if (st != GS_OK) return st;
+  StageTimer tm(ctx, ST_INIT, (hipStream_t)stream);
   return launch_init_points(xyz, n, *opts, seed, out, (hipStream_t)stream);
 }
 
@@ -407,21 +515,30 @@ gs_status gs_render_fwd(gs_ctx* ctx, gs_params params, const gs_camera* cams, in
   const uint32_t vn = (uint32_t)((size_t)f.views * (size_t)f.n);
 
   // 1. projection + SH
-  st = launch_preprocess_fwd(pd, f.vt, f, s);
+  {
+    StageTimer tm(ctx, ST_PROJECT, s);
+    st = launch_preprocess_fwd(pd, f.vt, f, s);
+  }
   if (st != GS_OK) return st;
   // 2. (view, Gaussian) entries in (depth bits, index) order
   int in_b = 0;
-  st = sort_pairs_u32(ctx, f.ss, (const uint32_t*)f.dkey.p, nullptr, (uint32_t*)f.dkw[0].p,
-                      (uint32_t*)f.sidx[0].p, (uint32_t*)f.dkw[1].p, (uint32_t*)f.sidx[1].p, vn,
-                      nullptr, 32, &in_b, s);
+  {
+    StageTimer tm(ctx, ST_DEPTH_SORT, s);
+    st = sort_pairs_u32(ctx, f.ss, (const uint32_t*)f.dkey.p, nullptr, (uint32_t*)f.dkw[0].p,
+                        (uint32_t*)f.sidx[0].p, (uint32_t*)f.dkw[1].p, (uint32_t*)f.sidx[1].p,
+                        vn, nullptr, 32, &in_b, s);
+  }
   if (st != GS_OK) return st;
   f.sidx_sel = in_b;
   const uint32_t* sidx = (const uint32_t*)f.sidx[in_b].p;
   // 3. record offsets and the total K (read back to size the record buffers)
   st = buf_ensure(ctx, f.ss.total, 16);
   if (st != GS_OK) return st;
-  st = scan_tile_counts(ctx, f.ss, sidx, (const uint2*)f.rect.p, vn, (uint32_t*)f.offs.p,
-                        (uint64_t*)f.ss.total.p, s);
+  {
+    StageTimer tm(ctx, ST_SCAN, s);
+    st = scan_tile_counts(ctx, f.ss, sidx, (const uint2*)f.rect.p, vn, (uint32_t*)f.offs.p,
+                          (uint64_t*)f.ss.total.p, s);
+  }
   if (st != GS_OK) return st;
   GS_HIP(hipMemcpyAsync(f.pinned, f.ss.total.p, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
   GS_HIP(hipStreamSynchronize(s));
@@ -438,16 +555,26 @@ gs_status gs_render_fwd(gs_ctx* ctx, gs_params params, const gs_camera* cams, in
     if (st != GS_OK) return st;
   }
   // 4. records in depth order, then the stable sort on the tile digits
-  st = launch_emit(f.vt, f, sidx, vn, s);
+  {
+    StageTimer tm(ctx, ST_EMIT, s);
+    st = launch_emit(f.vt, f, sidx, vn, s);
+  }
   if (st != GS_OK) return st;
-  st = sort_pairs_u32(ctx, f.ss, (const uint32_t*)f.tkey[0].p, (const uint32_t*)f.tval[0].p,
-                      (uint32_t*)f.tkey[1].p, (uint32_t*)f.tval[1].p, (uint32_t*)f.tkey[0].p,
-                      (uint32_t*)f.tval[0].p, (uint32_t)K, nullptr, f.key_bits, &in_b, s);
+  {
+    StageTimer tm(ctx, ST_TILE_SORT, s);
+    st = sort_pairs_u32(ctx, f.ss, (const uint32_t*)f.tkey[0].p, (const uint32_t*)f.tval[0].p,
+                        (uint32_t*)f.tkey[1].p, (uint32_t*)f.tval[1].p, (uint32_t*)f.tkey[0].p,
+                        (uint32_t*)f.tval[0].p, (uint32_t)K, nullptr, f.key_bits, &in_b, s);
+  }
   if (st != GS_OK) return st;
   f.tkey_sel = (K == 0) ? 0 : (in_b ? 0 : 1);
   // 5. per-tile ranges, 6. compositing
-  st = launch_ranges(f, s);
+  {
+    StageTimer tm(ctx, ST_RANGES, s);
+    st = launch_ranges(f, s);
+  }
   if (st != GS_OK) return st;
+  StageTimer tm(ctx, ST_BLEND_FWD, s);
   return launch_blend_fwd(f.vt, f, s);
 }
 
@@ -478,6 +605,7 @@ gs_status gs_loss_grad(gs_ctx* ctx, const float* const* rendered, const float* c
   }
   gs_status st = set_device(ctx);
   if (st != GS_OK) return st;
+  StageTimer tm(ctx, ST_LOSS, (hipStream_t)stream);
   return launch_loss(ctx, rendered, target, W, H, n_views, lambda_dssim, loss_out, dl_dimg,
                      (hipStream_t)stream);
 }
@@ -513,9 +641,10 @@ gs_status gs_render_bwd(gs_ctx* ctx, gs_frame* frame, gs_params params,
   if (st != GS_OK) return st;
   hipStream_t s = (hipStream_t)stream;
   if (f.K > 0) {
+    StageTimer tm(ctx, ST_BLEND_BWD, s);
     st = launch_blend_bwd(f.vt, f, s);
-    if (st != GS_OK) return st;
   }
+  if (st != GS_OK) return st;
   GradsDev g;
   g.means = grads.means;
   g.log_scales = grads.log_scales;
@@ -523,6 +652,7 @@ gs_status gs_render_bwd(gs_ctx* ctx, gs_frame* frame, gs_params params,
   g.logits = grads.opacity_logits;
   g.sh = grads.sh;
   g.accumulate = accumulate;
+  StageTimer tm(ctx, ST_PROJECT_BWD, s);
   return launch_preprocess_bwd(params_dev(params), f.vt, f, g, s);
 }
 
@@ -550,6 +680,7 @@ gs_status gs_adam_step(gs_ctx* ctx, gs_params p, gs_params g, gs_params m, gs_pa
   }
   gs_status st = set_device(ctx);
   if (st != GS_OK) return st;
+  StageTimer tm(ctx, ST_ADAM, (hipStream_t)stream);
   return launch_adam(p, g, m, v, *opts, step, (hipStream_t)stream);
 }
 

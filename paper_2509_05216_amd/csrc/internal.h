@@ -104,6 +104,17 @@ struct DevBuf {
 gs_status buf_ensure(Ctx* ctx, DevBuf& b, size_t bytes);
 void buf_free(Ctx* ctx, DevBuf& b);
 
+// Pipeline stages timed with HIP events when a context enables timing.
+enum Stage {
+  ST_PROJECT = 0, ST_DEPTH_SORT, ST_SCAN, ST_EMIT, ST_TILE_SORT, ST_RANGES, ST_BLEND_FWD,
+  ST_LOSS, ST_BLEND_BWD, ST_PROJECT_BWD, ST_ADAM, ST_INIT, ST_COUNT
+};
+
+struct PendingTiming {
+  int stage;
+  hipEvent_t a, b;
+};
+
 struct Ctx {
   int device = 0;
   size_t budget = 0;
@@ -112,9 +123,28 @@ struct Ctx {
   int cu_count = 0;
   hipDeviceProp_t prop;
   void* loss_scratch = nullptr;  // loss.hip workspace (g maps, block partials)
+  // stage timing
+  bool timing = false;
+  PendingTiming* pending = nullptr;
+  int n_pending = 0, cap_pending = 0;
+  hipEvent_t* free_events = nullptr;
+  int n_free = 0, cap_free = 0;
+  double stage_ms[ST_COUNT] = {0};
+  long long stage_count[ST_COUNT] = {0};
 };
 
 void free_loss_scratch(Ctx* ctx);
+
+// Records HIP events around a stage on stream s when the context times stages.
+struct StageTimer {
+  Ctx* c;
+  int stage;
+  hipStream_t s;
+  hipEvent_t a = nullptr;
+  StageTimer(Ctx* c_, int st, hipStream_t s_);
+  ~StageTimer();
+};
+gs_status timing_collect(Ctx* c);
 
 // Radix-sort / scan scratch.
 struct SortScratch {

@@ -1,22 +1,30 @@
 // Front-to-back alpha compositing of each tile's sorted list (forward) and its
 // reverse traversal (backward).
 //
-// One workgroup per tile, one pixel per thread (TILE x TILE threads: 1, 4 or
-// 16 waves).  The tile's records are staged through LDS in batches of DEPTH
-// splats (48 B each); every lane of a wave reads the same LDS address, so the
-// reads are broadcasts.  The forward stops a batch loop once every pixel of
-// the tile has terminated (block-wide vote).
+// One workgroup per tile, one pixel per thread (TILE x TILE threads).  Each
+// wave owns an 8 x 8 block of the tile.  The tile's records are staged
+// through LDS in batches of DEPTH splats; every lane of a wave reads the same
+// LDS address (broadcast).  When a splat is staged its loader also computes
+// the axis-aligned box outside which alpha < 1/255 for certain (the ellipse
+// power >= -ln(255 o), widened by a safety margin) and tests it against the
+// tile's 8 x 8 wave blocks; a ballot/popcount compaction then gives every wave
+// the ordered list of staged splats that can touch its block, and the wave
+// walks only that list.  Skipped pairs would be rejected by the alpha test
+// anyway, so results are unchanged and most of the per-pair work disappears.
 //
-// The backward walks the list from the tile's last contributor down to its
-// first, recomputing each pixel's transmittance as T / (1 - alpha) from the
-// final value, so no per-pixel list is stored.  Per-pair gradients (9 floats)
-// are summed over the wave with cross-lane shuffles, combined across the
-// workgroup's waves with LDS float atomics, and added to the per-Gaussian
-// accumulators with one global atomic per component per (tile, Gaussian).
+// The forward stops a batch loop once every pixel of the tile has terminated
+// (block-wide vote).  The backward walks the list from the tile's last
+// contributor down to its first, recomputing each pixel's transmittance as
+// T / (1 - alpha) from the final value, so no per-pixel list is stored.
+// Per-pair gradients (9 floats) are reduce-scattered across the wave (two
+// gfx950 permlane swaps, then DPP steps inside 16-lane rows: about 28 VALU
+// instructions for all nine sums), added across the workgroup's waves with
+// LDS float atomics and to the per-Gaussian accumulators with one global
+// atomic per component per (tile, Gaussian).
 //
 // Both kernels evaluate a pair with the same inline code; the library is
-// compiled with -ffp-contract=off, so the forward's skip/stop decisions are
-// reproduced exactly by the backward.
+// compiled with -ffp-contract=off, so the backward reproduces the forward's
+// skip/stop decisions exactly.
 #include "internal.h"
 
 namespace isogs {
@@ -26,22 +34,6 @@ constexpr float kAlphaMin = 1.0f / 255.0f;
 constexpr float kAlphaMax = 0.99f;
 constexpr float kTMin = 1e-4f;
 
-struct SplatL {
-  float A, B, C, o;
-  int cx, cy;
-  float fx, fy;
-  float r, g, b, depth;
-};
-
-__device__ inline SplatL to_splat(float4 q0, float4 q1, float4 q2) {
-  SplatL s;
-  s.A = q0.x; s.B = q0.y; s.C = q0.z; s.o = q0.w;
-  s.cx = __float_as_int(q1.x); s.cy = __float_as_int(q1.y);
-  s.fx = q1.z; s.fy = q1.w;
-  s.r = q2.x; s.g = q2.y; s.b = q2.z; s.depth = q2.w;
-  return s;
-}
-
 // power = -1/2 (A dx^2 + C dy^2) - B dx dy at pixel (px, py); dx = px + 0.5 - mean_x.
 __device__ inline void pair_eval(float A, float B, float C, int cx, int cy, float fx, float fy,
                                  int px, int py, float& dx, float& dy, float& power) {
@@ -49,6 +41,107 @@ __device__ inline void pair_eval(float A, float B, float C, int cx, int cy, floa
   dy = (float)(py - cy) + fy;
   power = -0.5f * (A * dx * dx + C * dy * dy) - B * dx * dy;
 }
+
+// Conservative box of the alpha >= 1/255 region: (mean_x, mean_y, half_w, half_h);
+// half_w < 0 when the splat can never pass the alpha test.
+__device__ inline float4 splat_box(float4 q0, float4 q1) {
+  const float A = q0.x, B = q0.y, C = q0.z, o = q0.w;
+  const float mx = (float)__float_as_int(q1.x) + 0.5f - q1.z;
+  const float my = (float)__float_as_int(q1.y) + 0.5f - q1.w;
+  const float lim = o * 255.0f;
+  // determinant in float64: the float32 conic of an elongated splat loses digits here
+  const double det = (double)A * (double)C - (double)B * (double)B;
+  if (!(lim >= 1.0f) || !(det > 0.0)) return make_float4(mx, my, -1.f, -1.f);
+  const double c2 = 2.0 * ((double)logf(lim) + 1e-3);  // bound of dx^T Q dx, with margin
+  const float hw = (float)(sqrt(c2 * (double)C / det) * 1.01 + 1e-2);
+  const float hh = (float)(sqrt(c2 * (double)A / det) * 1.01 + 1e-2);
+  return make_float4(mx, my, hw, hh);
+}
+
+// True when the box misses the 8 x 8 block whose first pixel is (bx0, by0).
+__device__ inline bool box_misses(float4 b, int bx0, int by0) {
+  const float x0 = (float)bx0 + 0.5f, y0 = (float)by0 + 0.5f;
+  return b.z < 0.f || b.x + b.z < x0 || b.x - b.z > x0 + 7.0f || b.y + b.w < y0 ||
+         b.y - b.w > y0 + 7.0f;
+}
+
+
+// Stage records [base, base + cnt) of the tile list into LDS and build, for
+// every wave, the ascending list of batch slots whose alpha box overlaps the
+// wave's 8 x 8 block (ballot + popcount compaction; DEPTH <= threads).
+template <int NT, int DEPTH>
+struct Stage {
+  static constexpr int NW = NT / 64;
+  float4 s0[DEPTH], s1[DEPTH], s2[DEPTH];
+  uint32_t sidx[DEPTH];
+  uint16_t list[NW][DEPTH];
+  uint32_t chunk[NW][DEPTH / 64 + 1];
+  uint32_t count[NW];
+};
+
+template <int TILE, int DEPTH>
+__device__ inline void stage_batch(Stage<TILE * TILE, DEPTH>& st, const uint32_t* __restrict__ tval,
+                                   const float4* __restrict__ splat, uint32_t base, int cnt,
+                                   int tile_x0, int tile_y0) {
+  constexpr int NT = TILE * TILE;
+  constexpr int NW = NT / 64;
+  constexpr int BPR = TILE / 8;
+  const int t = threadIdx.x;
+  const int lane = __lane_id(), wave = t / 64;
+  uint32_t mask = 0;
+  if (t < cnt) {
+    const uint32_t idx = tval[base + t];
+    const float4 q0 = splat[(size_t)idx * 3 + 0], q1 = splat[(size_t)idx * 3 + 1];
+    st.sidx[t] = idx;
+    st.s0[t] = q0;
+    st.s1[t] = q1;
+    st.s2[t] = splat[(size_t)idx * 3 + 2];
+    const float4 b = splat_box(q0, q1);
+#pragma unroll
+    for (int w = 0; w < NW; ++w)
+      if (!box_misses(b, tile_x0 + (w % BPR) * 8, tile_y0 + (w / BPR) * 8)) mask |= 1u << w;
+  }
+  const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
+  uint32_t rank[NW];
+  if (t < DEPTH) {
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+      const uint64_t bal = __ballot((mask >> w) & 1u);
+      rank[w] = (uint32_t)__popcll(bal & lt);
+      if (lane == 0) st.chunk[w][wave] = (uint32_t)__popcll(bal);
+    }
+  }
+  __syncthreads();
+  if (t < DEPTH) {
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+      if ((mask >> w) & 1u) {
+        uint32_t off = rank[w];
+        for (int c = 0; c < wave; ++c) off += st.chunk[w][c];
+        st.list[w][off] = (uint16_t)t;
+      }
+      if (t == 0) {
+        uint32_t tot = 0;
+        for (int c = 0; c < (DEPTH + 63) / 64; ++c) tot += st.chunk[w][c];
+        st.count[w] = tot;
+      }
+    }
+  }
+  __syncthreads();
+}
+
+template <int TILE>
+struct Layout {
+  static constexpr int NT = TILE * TILE;
+  static constexpr int BPR = TILE / 8;  // 8x8 blocks per tile row
+  __device__ static void pixel(int tile_x, int tile_y, int& px, int& py, int& bx0, int& by0) {
+    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+    bx0 = tile_x * TILE + (wave % BPR) * 8;
+    by0 = tile_y * TILE + (wave / BPR) * 8;
+    px = bx0 + (lane & 7);
+    py = by0 + (lane >> 3);
+  }
+};
 
 template <int TILE, int DEPTH>
 __global__ __launch_bounds__(TILE* TILE) void k_blend_fwd(ViewTable vt,
@@ -58,14 +151,15 @@ __global__ __launch_bounds__(TILE* TILE) void k_blend_fwd(ViewTable vt,
                                                           float* __restrict__ finalT,
                                                           uint32_t* __restrict__ ncon) {
   constexpr int NT = TILE * TILE;
-  __shared__ float4 s0[DEPTH], s1[DEPTH], s2[DEPTH];
+  __shared__ Stage<NT, DEPTH> st;
   const int gt = blockIdx.x;
   const int v = view_of_tile(vt, gt);
   const CamDev& cam = vt.v[v];
   const int lt = gt - cam.tile_offset;
-  const int tx = lt % cam.tiles_x, ty = lt / cam.tiles_x;
-  const int px = tx * TILE + (int)(threadIdx.x % TILE);
-  const int py = ty * TILE + (int)(threadIdx.x / TILE);
+  const int tile_x = lt % cam.tiles_x, tile_y = lt / cam.tiles_x;
+  int px, py, bx0, by0;
+  Layout<TILE>::pixel(tile_x, tile_y, px, py, bx0, by0);
+  const int wave = threadIdx.x / 64;
   const bool inside = px < cam.W && py < cam.H;
   const uint2 rg = ranges[gt];
   float T = 1.f, cr = 0.f, cg = 0.f, cb = 0.f;
@@ -74,16 +168,12 @@ __global__ __launch_bounds__(TILE* TILE) void k_blend_fwd(ViewTable vt,
   for (uint32_t base = rg.x; base < rg.y; base += DEPTH) {
     if (__syncthreads_count(done) == NT) break;
     const int cnt = (int)min((uint32_t)DEPTH, rg.y - base);
-    for (int j = threadIdx.x; j < cnt; j += NT) {
-      const size_t idx = tval[base + j];
-      s0[j] = splat[idx * 3 + 0];
-      s1[j] = splat[idx * 3 + 1];
-      s2[j] = splat[idx * 3 + 2];
-    }
-    __syncthreads();
+    stage_batch<TILE, DEPTH>(st, tval, splat, base, cnt, tile_x * TILE, tile_y * TILE);
+    const int nw = (int)st.count[wave];
     if (!done) {
-      for (int j = 0; j < cnt; ++j) {
-        const float4 q0 = s0[j], q1 = s1[j];
+      for (int k = 0; k < nw; ++k) {
+        const int j = st.list[wave][k];
+        const float4 q0 = st.s0[j], q1 = st.s1[j];
         float dx, dy, power;
         pair_eval(q0.x, q0.y, q0.z, __float_as_int(q1.x), __float_as_int(q1.y), q1.z, q1.w, px,
                   py, dx, dy, power);
@@ -95,7 +185,7 @@ __global__ __launch_bounds__(TILE* TILE) void k_blend_fwd(ViewTable vt,
           done = true;
           break;
         }
-        const float4 q2 = s2[j];
+        const float4 q2 = st.s2[j];
         const float w = alpha * T;
         cr += q2.x * w;
         cg += q2.y * w;
@@ -116,10 +206,63 @@ __global__ __launch_bounds__(TILE* TILE) void k_blend_fwd(ViewTable vt,
   }
 }
 
-__device__ inline float wave_sum(float x) {
-#pragma unroll
-  for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d, 64);
+// ---------------------------------------------------------------- reduction
+__device__ inline float dpp_f(float x, int ctrl) {
+  // row_mask / bank_mask all lanes, bound_ctrl off: every source lane is valid here
+  switch (ctrl) {
+    case 0xB1: return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0xB1, 0xF, 0xF, false));
+    case 0x4E: return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x4E, 0xF, 0xF, false));
+    case 0x141: return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x141, 0xF, 0xF, false));
+    default: return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x128, 0xF, 0xF, false));
+  }
+}
+
+// Sum of x over the 16 lanes of each row, in every lane of the row.
+__device__ inline float row_sum16(float x) {
+  x += dpp_f(x, 0xB1);   // quad_perm [1,0,3,2]: pairs l, l^1
+  x += dpp_f(x, 0x4E);   // quad_perm [2,3,0,1]: pairs l, l^2
+  x += dpp_f(x, 0x141);  // row_half_mirror: quad 0 <-> quad 1 within each 8 lanes
+  x += dpp_f(x, 0x128);  // row_ror:8: the two halves of the row
   return x;
+}
+
+// (a + partner) where lanes 0-31 pair with 32-63: lower lanes get a's sum,
+// upper lanes b's sum.
+__device__ inline float swap32_sum(float a, float b) {
+  auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+// Rows 0 and 2 get the xor-16 pair sum of a, rows 1 and 3 that of b.
+__device__ inline float swap16_sum(float a, float b) {
+  auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+// Reduce g[0..8] over the wave and add each sum to part[k] with one LDS atomic.
+// After the xor-32 step lanes 0-31 carry values {0..4} and lanes 32-63 {5..8};
+// after the xor-16 step row r, slot m carries value (r>>1)*5 + 2m + (r&1).
+__device__ inline void wave_reduce_add(const float* g, float* part) {
+  const float a0 = swap32_sum(g[0], g[5]);
+  const float a1 = swap32_sum(g[1], g[6]);
+  const float a2 = swap32_sum(g[2], g[7]);
+  const float a3 = swap32_sum(g[3], g[8]);
+  const float a4 = swap32_sum(g[4], 0.f);
+  const float b0 = row_sum16(swap16_sum(a0, a1));
+  const float b1 = row_sum16(swap16_sum(a2, a3));
+  const float b2 = row_sum16(swap16_sum(a4, 0.f));
+  const int lane = __lane_id();
+  const int row = lane >> 4, m = lane & 15;
+  if (m < 3) {
+    const int hi = row >> 1, odd = row & 1;
+    const int aslot = 2 * m + odd;
+    const bool valid = hi ? (aslot <= 3) : (aslot <= 4);
+    if (valid) {
+      const int k = hi ? 5 + aslot : aslot;
+      const float s = (m == 0) ? b0 : ((m == 1) ? b1 : b2);
+      if (s != 0.f) atomicAdd(&part[k], s);
+    }
+  }
 }
 
 template <int TILE, int DEPTH>
@@ -132,17 +275,16 @@ __global__ __launch_bounds__(TILE* TILE) void k_blend_bwd(ViewTable vt, int n_ga
                                                           float* __restrict__ acc) {
   constexpr int NT = TILE * TILE;
   constexpr int NW = NT / 64;
-  __shared__ float4 s0[DEPTH], s1[DEPTH], s2[DEPTH];
-  __shared__ uint32_t sidx[DEPTH];
+  __shared__ Stage<NT, DEPTH> st;
   __shared__ float part[DEPTH * 9];
   __shared__ uint32_t smax[NW];
   const int gt = blockIdx.x;
   const int v = view_of_tile(vt, gt);
   const CamDev& cam = vt.v[v];
   const int lt = gt - cam.tile_offset;
-  const int tx = lt % cam.tiles_x, ty = lt / cam.tiles_x;
-  const int px = tx * TILE + (int)(threadIdx.x % TILE);
-  const int py = ty * TILE + (int)(threadIdx.x / TILE);
+  const int tile_x = lt % cam.tiles_x, tile_y = lt / cam.tiles_x;
+  int px, py, bx0, by0;
+  Layout<TILE>::pixel(tile_x, tile_y, px, py, bx0, by0);
   const bool inside = px < cam.W && py < cam.H;
   const uint2 rg = ranges[gt];
   const int lane = __lane_id(), wave = threadIdx.x / 64;
@@ -160,10 +302,11 @@ __global__ __launch_bounds__(TILE* TILE) void k_blend_bwd(ViewTable vt, int n_ga
   }
   // colour composited behind the current record (starts with T_final * bg)
   float Sr = T * vt.bg[0], Sg = T * vt.bg[1], Sb = T * vt.bg[2];
-  // tile-wide last contributor
+  // last contributor of the wave and of the tile
   uint32_t m = nc;
 #pragma unroll
   for (int d = 32; d >= 1; d >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, d, 64));
+  const int wave_n = (int)m;
   if (lane == 0) smax[wave] = m;
   __syncthreads();
   uint32_t maxn = 0;
@@ -173,23 +316,21 @@ __global__ __launch_bounds__(TILE* TILE) void k_blend_bwd(ViewTable vt, int n_ga
     const int lo = max(0, hi - DEPTH);
     const int cnt = hi - lo;
     __syncthreads();
-    for (int j = threadIdx.x; j < cnt; j += NT) {
-      const uint32_t idx = tval[rg.x + lo + j];
-      sidx[j] = idx;
-      s0[j] = splat[(size_t)idx * 3 + 0];
-      s1[j] = splat[(size_t)idx * 3 + 1];
-      s2[j] = splat[(size_t)idx * 3 + 2];
-    }
     for (int j = threadIdx.x; j < cnt * 9; j += NT) part[j] = 0.f;
-    __syncthreads();
-    for (int j = cnt - 1; j >= 0; --j) {
+    stage_batch<TILE, DEPTH>(st, tval, splat, rg.x + (uint32_t)lo, cnt, tile_x * TILE,
+                             tile_y * TILE);
+    // walk this wave's overlapping slots from the back, below its last contributor
+    int k = (int)st.count[wave] - 1;
+    while (k >= 0 && lo + (int)st.list[wave][k] >= wave_n) --k;
+    for (; k >= 0; --k) {
+      const int j = st.list[wave][k];
       const int pos = lo + j;  // position in the tile list
       float g[9];
 #pragma unroll
-      for (int k = 0; k < 9; ++k) g[k] = 0.f;
+      for (int q = 0; q < 9; ++q) g[q] = 0.f;
       bool contrib = inside && (uint32_t)pos < nc;
       if (contrib) {
-        const float4 q0 = s0[j], q1 = s1[j];
+        const float4 q0 = st.s0[j], q1 = st.s1[j];
         float dx, dy, power;
         pair_eval(q0.x, q0.y, q0.z, __float_as_int(q1.x), __float_as_int(q1.y), q1.z, q1.w, px,
                   py, dx, dy, power);
@@ -199,7 +340,7 @@ __global__ __launch_bounds__(TILE* TILE) void k_blend_bwd(ViewTable vt, int n_ga
         if (power > 0.f || alpha < kAlphaMin) {
           contrib = false;
         } else {
-          const float4 q2 = s2[j];
+          const float4 q2 = st.s2[j];
           const float oma = 1.f - alpha;
           T = T / oma;  // transmittance before this record
           const float w = alpha * T;
@@ -222,22 +363,16 @@ __global__ __launch_bounds__(TILE* TILE) void k_blend_bwd(ViewTable vt, int n_ga
           }
         }
       }
-      if (__any(contrib)) {
-#pragma unroll
-        for (int k = 0; k < 9; ++k) {
-          const float s = wave_sum(g[k]);
-          if (lane == 0 && s != 0.f) atomicAdd(&part[j * 9 + k], s);
-        }
-      }
+      if (__any(contrib)) wave_reduce_add(g, &part[j * 9]);
     }
     __syncthreads();
     for (int t = threadIdx.x; t < cnt * 9; t += NT) {
       const float s = part[t];
       if (s != 0.f) {
-        const int j = t / 9, k = t - j * 9;
-        const uint32_t idx = sidx[j];
+        const int j = t / 9, c = t - j * 9;
+        const uint32_t idx = st.sidx[j];
         const uint32_t vv = idx / (uint32_t)n_gauss, gi = idx - vv * (uint32_t)n_gauss;
-        atomicAdd(acc + ((size_t)vv * 9 + k) * n_gauss + gi, s);
+        atomicAdd(acc + ((size_t)vv * 9 + c) * n_gauss + gi, s);
       }
     }
   }

@@ -272,6 +272,19 @@ def main():
     ctx.set_timing(False)
     nb = (scene.params["sh_degree"] + 1) ** 2 * 3 + 11
     adam_gbs = 28 * nb * n / (adam_ms * 1e-3) / 1e9
+    # achievable HBM bandwidth: plain copy of 2 GiB (read + write)
+    probe_bytes = 2 << 30
+    src = torch.ones(probe_bytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    P.bw_probe(ctx, src, dst)
+    torch.cuda.synchronize()
+    ctx.set_timing(True)
+    for _ in range(5):
+        P.bw_probe(ctx, src, dst)
+    probe_ms = ctx.stage_times()["probe"][0] / 5
+    ctx.set_timing(False)
+    probe_gbs = 2 * probe_bytes / (probe_ms * 1e-3) / 1e9
+    del src, dst
 
     head = res.get("batched") or res["plain"]
     form = "batched" if "batched" in res else "plain"
@@ -299,7 +312,10 @@ def main():
                                              for s, (t, c) in r["stages"].items() if c}}
                   for k, r in res.items()},
         "adam": {"ms": round(adam_ms, 4), "GBps_algorithmic": round(adam_gbs, 1),
+                 "frac_of_probe": round(adam_gbs / probe_gbs, 4),
                  "step_ms_with_adam": round(head["ms"] + adam_ms, 3)},
+        "hbm_probe": {"GBps": round(probe_gbs, 1), "bytes_per_launch": 2 * probe_bytes,
+                      "ms": round(probe_ms, 4), "frac_of_peak": round(probe_gbs / HBM_PEAK_GBS, 4)},
     }
     if not args.no_cpu_baseline:
         t0 = time.perf_counter()

@@ -161,7 +161,7 @@ gs_status gs_ctx_memory(gs_ctx* ctx, size_t* in_use, size_t* peak);
  * waits for the recorded events and returns the summed duration (ms) and the
  * number of timed launches of one stage; gs_stage_name gives the stage's name
  * ("project", "depth_sort", "scan", "emit", "tile_sort", "ranges",
- * "blend_fwd", "loss", "blend_bwd", "project_bwd", "adam", "init") or NULL
+ * "blend_fwd", "loss", "blend_bwd", "project_bwd", "adam", "init", "probe") or NULL
  * past the last stage. */
 gs_status gs_ctx_set_timing(gs_ctx* ctx, int32_t enable);
 gs_status gs_ctx_stage_time(gs_ctx* ctx, int32_t stage, double* total_ms, int64_t* launches);
@@ -219,6 +219,12 @@ gs_status gs_render_bwd(gs_ctx* ctx, gs_frame* frame, gs_params params,
 gs_status gs_adam_step(gs_ctx* ctx, gs_params p, gs_params g, gs_params m,
                        gs_params v, const gs_adam_opts* opts, int64_t step,
                        void* stream);
+
+/* Achievable-bandwidth probe: copy `bytes` (multiple of 16) from src to dst,
+ * both device, 16-byte aligned, with a plain grid-stride kernel.  Timed as
+ * stage "probe" when timing is enabled.  Not part of the method: it gives the
+ * HBM roofline denominator and calibrates traffic counters. */
+gs_status gs_bw_probe(gs_ctx* ctx, const void* src, void* dst, size_t bytes, void* stream);
 
 gs_status gs_frame_stats_get(gs_frame* frame, gs_frame_stats* out);
 /* Copy a frame buffer (see gs_export) for view `view` (-1 = all views) into

@@ -3,7 +3,7 @@ isosurface visualization (hot path of 3D-GS training: EWA projection, SH
 colour, tile binning and sort, alpha compositing, its backward, the loss
 gradient and Adam), behind the C ABI of include/isogs.h."""
 from ._lib import IsogsError, lib  # noqa: F401
-from .core import (Context, Frame, Params, adam_step, camera, camera_from_dict,  # noqa: F401
+from .core import (Context, Frame, Params, adam_step, bw_probe, camera, camera_from_dict,  # noqa: F401
                    camera_to_dict, init_from_points, loss_grad, orbit_cameras, render_bwd,
                    render_fwd)
 from .autograd import RasterizeFn, rasterize  # noqa: F401

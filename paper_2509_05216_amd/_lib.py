@@ -90,6 +90,7 @@ SIGNATURES = [
     ("gs_render_bwd", C.c_int, [_P, _P, GsParams, _PP, GsParams, C.c_int32, _P]),
     ("gs_adam_step", C.c_int, [_P, GsParams, GsParams, GsParams, GsParams,
                                C.POINTER(GsAdamOpts), C.c_int64, _P]),
+    ("gs_bw_probe", C.c_int, [_P, _P, _P, C.c_size_t, _P]),
     ("gs_frame_stats_get", C.c_int, [_P, C.POINTER(GsFrameStats)]),
     ("gs_frame_export", C.c_int, [_P, C.c_int32, C.c_int32, _P, C.c_size_t, _P]),
     ("gs_frame_release", None, [_P]),

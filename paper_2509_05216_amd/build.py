@@ -18,7 +18,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libisogs.so")
-SOURCES = ["api.hip", "preprocess.hip", "sort.hip", "blend.hip", "loss.hip", "adam.hip"]
+SOURCES = ["api.hip", "preprocess.hip", "sort.hip", "blend.hip", "loss.hip", "adam.hip",
+           "probe.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -284,3 +284,9 @@ def init_from_points(ctx, xyz, sh_degree, *, log_scale=0.0, log_scale_jitter=0.0
     L.check(L.lib().gs_init_from_points(ctx.handle, _ptr(xyz.contiguous()), n, C.byref(o),
                                         C.c_uint64(seed), p.abi(), _stream(stream)))
     return p
+
+
+def bw_probe(ctx, src, dst, stream=None):
+    """Copy src -> dst (same-size contiguous device tensors) with the probe kernel."""
+    nbytes = src.numel() * src.element_size()
+    L.check(L.lib().gs_bw_probe(ctx.handle, _ptr(src), _ptr(dst), nbytes, _stream(stream)))

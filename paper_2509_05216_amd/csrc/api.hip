@@ -126,7 +126,7 @@ gs_status timing_collect(Ctx* c) {
 
 static const char* kStageNames[ST_COUNT] = {
     "project", "depth_sort", "scan", "emit", "tile_sort", "ranges", "blend_fwd",
-    "loss", "blend_bwd", "project_bwd", "adam", "init"};
+    "loss", "blend_bwd", "project_bwd", "adam", "init", "probe"};
 
 size_t Frame::bytes() const {
   size_t s = splat.cap + rect.cap + dkey.cap + dkw[0].cap + dkw[1].cap + sidx[0].cap +
@@ -682,6 +682,18 @@ gs_status gs_adam_step(gs_ctx* ctx, gs_params p, gs_params g, gs_params m, gs_pa
   if (st != GS_OK) return st;
   StageTimer tm(ctx, ST_ADAM, (hipStream_t)stream);
   return launch_adam(p, g, m, v, *opts, step, (hipStream_t)stream);
+}
+
+gs_status gs_bw_probe(gs_ctx* ctx, const void* src, void* dst, size_t bytes, void* stream) {
+  if (ctx == nullptr || src == nullptr || dst == nullptr || bytes % 16 != 0 ||
+      ((uintptr_t)src & 15u) != 0 || ((uintptr_t)dst & 15u) != 0) {
+    set_error("gs_bw_probe: null pointer, or size / address not a multiple of 16");
+    return GS_ERR_INVALID;
+  }
+  gs_status st = set_device(ctx);
+  if (st != GS_OK) return st;
+  StageTimer tm(ctx, ST_PROBE, (hipStream_t)stream);
+  return launch_copy_probe(ctx, src, dst, bytes, (hipStream_t)stream);
 }
 
 gs_status gs_frame_stats_get(gs_frame* frame, gs_frame_stats* out) {

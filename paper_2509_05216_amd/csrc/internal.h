@@ -107,7 +107,7 @@ void buf_free(Ctx* ctx, DevBuf& b);
 // Pipeline stages timed with HIP events when a context enables timing.
 enum Stage {
   ST_PROJECT = 0, ST_DEPTH_SORT, ST_SCAN, ST_EMIT, ST_TILE_SORT, ST_RANGES, ST_BLEND_FWD,
-  ST_LOSS, ST_BLEND_BWD, ST_PROJECT_BWD, ST_ADAM, ST_INIT, ST_COUNT
+  ST_LOSS, ST_BLEND_BWD, ST_PROJECT_BWD, ST_ADAM, ST_INIT, ST_PROBE, ST_COUNT
 };
 
 struct PendingTiming {
@@ -204,6 +204,8 @@ gs_status launch_blend_bwd(const ViewTable& vt, Frame& f, hipStream_t s);
 gs_status launch_loss(Ctx* ctx, const float* const* x, const float* const* y, const int* W,
                       const int* H, int nv, float lambda, float* loss_out, float* const* dl,
                       hipStream_t s);
+// probe.hip
+gs_status launch_copy_probe(Ctx* ctx, const void* src, void* dst, size_t bytes, hipStream_t s);
 // adam.hip
 gs_status launch_adam(const gs_params& p, const gs_params& g, const gs_params& m,
                       const gs_params& v, const gs_adam_opts& o, int64_t step, hipStream_t s);

@@ -34,6 +34,25 @@ FP32_PEAK_TFLOPS = 157.3
 # algorithmic FLOP per (pixel, list position up to the pixel's last contributor)
 FLOP_PAIR_FWD = 23
 FLOP_PAIR_BWD = 68
+# HBM bytes per launch of a kernel, from calibrated rocprofv3 FETCH_SIZE / WRITE_SIZE runs
+# (profiles/hbm_traffic_kingsnake4m.md), valid only while the kernel source is unchanged:
+# the figure is dropped (traffic = null) when the source hash no longer matches.
+MEASURED_TRAFFIC = {
+    "blend_bwd": {"source": "paper_2509_05216_amd/csrc/blend.hip",
+                  "sha256": "1953ad7eb534dcf81ae396938eaec72fad9b5229af48b87b292def31cf2c98aa",
+                  "read_bytes": 2887.4e6, "write_bytes": 3893.5e6, "views": 4},
+}
+
+
+def measured_traffic(kernel, views):
+    import hashlib
+    m = MEASURED_TRAFFIC.get(kernel)
+    if m is None or m["views"] != views:
+        return None
+    with open(os.path.join(ROOT, m["source"]), "rb") as fh:
+        if hashlib.sha256(fh.read()).hexdigest() != m["sha256"]:
+            return None
+    return round(m["read_bytes"] + m["write_bytes"])
 
 
 def log(msg):
@@ -291,6 +310,7 @@ def main():
     value = head["pixels"] / (head["ms"] * 1e-3) / 1e6
     dom, roof = roofline(head["stages"], args.steps, n, head["views"], head["visible"], head["K"],
                          head["pixels"], head["pairs"])
+    roof["traffic"] = measured_traffic(dom, head["views"]) if args.n is None else None
     out = {
         "metric": METRIC, "value": round(value, 3), "unit": "Mpix/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(head["ms"], 3),

@@ -132,7 +132,7 @@ typedef enum {
   GS_EXPORT_RANGES = 2,     /* uint32[n_tiles][2]: [start, end) per global tile */
   GS_EXPORT_FINAL_T = 3,    /* float[n_pixels]: transmittance left after blending */
   GS_EXPORT_N_CONTRIB = 4,  /* uint32[n_pixels]: position + 1 of the last contributor */
-  GS_EXPORT_SCREEN_GRADS = 5, /* float[n_views][9][n]: dL/d(m_x, m_y, A, B, C, opacity, r, g, b) */
+  GS_EXPORT_SCREEN_GRADS = 5, /* float[n_views][n][12]: dL/d(m_x, m_y, A, B, C, opacity, r, g, b), 3 pad */
   GS_EXPORT_SPLATS = 6,     /* float[n_views][n][12]: A, B, C, o, mx, my, -, -, r, g, b, depth */
   GS_EXPORT_RECTS = 7       /* uint32[n_views][n][2]: tile x0 | y0 << 16, x1 | y1 << 16
                                (x1 < x0 when the Gaussian touches no tile) */

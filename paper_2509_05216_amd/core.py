@@ -178,7 +178,7 @@ class Frame:
                               else torch.int32, device=device)
             count = None
         elif what == "screen_grads":
-            out = torch.empty(st["n_views"] * 9 * n, dtype=torch.float32, device=device)
+            out = torch.empty(st["n_views"] * 12 * n, dtype=torch.float32, device=device)
             count = None
         elif what == "splats":
             out = torch.empty(st["n_views"] * n * 12, dtype=torch.float32, device=device)

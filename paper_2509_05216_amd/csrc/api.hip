@@ -254,7 +254,7 @@ static gs_status frame_buffers(Frame& f) {
   ENS(f.ranges, (size_t)f.vt.total_tiles * 8);
   ENS(f.finalT, (size_t)f.total_pix * 4);
   ENS(f.ncon, (size_t)f.total_pix * 4);
-  const size_t acc_bytes = (size_t)f.views * 9 * (size_t)f.n * 4;
+  const size_t acc_bytes = (size_t)f.views * kAccStride * (size_t)f.n * 4;
   if (f.acc.cap < acc_bytes) {
     ENS(f.acc, acc_bytes);
     f.acc_zeroed = false;
@@ -506,7 +506,7 @@ gs_status gs_render_fwd(gs_ctx* ctx, gs_params params, const gs_camera* cams, in
     return st;
   }
   if (!f.acc_zeroed) {
-    st = launch_fill_u32(f.acc.p, 0u, (size_t)f.views * 9 * (size_t)f.n, s);
+    st = launch_fill_u32(f.acc.p, 0u, (size_t)f.views * kAccStride * (size_t)f.n, s);
     if (st != GS_OK) return st;
     f.acc_zeroed = true;
   }
@@ -761,10 +761,10 @@ gs_status gs_frame_export(gs_frame* frame, int32_t what, int32_t view, void* dst
       break;
     case GS_EXPORT_SCREEN_GRADS:
       src = f.acc.p;
-      need = (size_t)f.views * 9 * n * 4;
+      need = (size_t)f.views * kAccStride * n * 4;
       if (view >= 0) {
-        off = (size_t)view * 9 * n * 4;
-        need = 9 * n * 4;
+        off = (size_t)view * kAccStride * n * 4;
+        need = kAccStride * n * 4;
       }
       break;
     case GS_EXPORT_SPLATS:

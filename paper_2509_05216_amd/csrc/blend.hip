@@ -370,9 +370,9 @@ __global__ __launch_bounds__(TILE* TILE) void k_blend_bwd(ViewTable vt, int n_ga
       const float s = part[t];
       if (s != 0.f) {
         const int j = t / 9, c = t - j * 9;
-        const uint32_t idx = st.sidx[j];
-        const uint32_t vv = idx / (uint32_t)n_gauss, gi = idx - vv * (uint32_t)n_gauss;
-        atomicAdd(acc + ((size_t)vv * 9 + c) * n_gauss + gi, s);
+        // AoS accumulators: the nine components of a (view, Gaussian) are adjacent,
+        // so neighbouring lanes' atomics fall in one or two cache lines
+        atomicAdd(acc + (size_t)st.sidx[j] * kAccStride + c, s);
       }
     }
   }

@@ -27,6 +27,9 @@
 namespace isogs {
 
 constexpr int kMaxViews = 16;
+// Screen-gradient accumulator record: dL/d(mx, my, A, B, C, opacity, r, g, b) + 3 pad floats,
+// one record per (view, Gaussian), 16-byte aligned.
+constexpr int kAccStride = 12;
 
 struct CamDev {
   float R[9];

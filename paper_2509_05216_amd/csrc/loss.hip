@@ -165,29 +165,53 @@ struct LossRed {
   double inv_count[kMaxViews];
 };
 
-__global__ __launch_bounds__(256) void k_loss_reduce(const double* __restrict__ part, LossRed lr,
-                                                     float lambda, float* __restrict__ out) {
+constexpr int kRedBlocks = 64;
+
+__device__ inline void block_sum2(double& a, double& b) {
   __shared__ double sh[2][256];
+  sh[0][threadIdx.x] = a;
+  sh[1][threadIdx.x] = b;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) {
+      sh[0][threadIdx.x] += sh[0][threadIdx.x + st];
+      sh[1][threadIdx.x] += sh[1][threadIdx.x + st];
+    }
+    __syncthreads();
+  }
+  a = sh[0][0];
+  b = sh[1][0];
+  __syncthreads();
+}
+
+// Stage 1: block (b, v) sums view v's partials b, b + 64, ... (fixed order).
+__global__ __launch_bounds__(256) void k_loss_partial(const double* __restrict__ part, LossRed lr,
+                                                      double* __restrict__ part2) {
+  const int v = blockIdx.y;
+  double a = 0.0, b = 0.0;
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < lr.nblk[v]; i += kRedBlocks * 256) {
+    a += part[2 * (lr.off[v] + i) + 0];
+    b += part[2 * (lr.off[v] + i) + 1];
+  }
+  block_sum2(a, b);
+  if (threadIdx.x == 0) {
+    part2[2 * (v * kRedBlocks + blockIdx.x) + 0] = a;
+    part2[2 * (v * kRedBlocks + blockIdx.x) + 1] = b;
+  }
+}
+
+// Stage 2: one block combines the per-view sums into the loss.
+__global__ __launch_bounds__(256) void k_loss_final(const double* __restrict__ part2, LossRed lr,
+                                                    float lambda, float* __restrict__ out) {
   double total = 0.0;
   for (int v = 0; v < lr.nv; ++v) {
     double a = 0.0, b = 0.0;
-    for (int i = threadIdx.x; i < lr.nblk[v]; i += 256) {
-      a += part[2 * (lr.off[v] + i) + 0];
-      b += part[2 * (lr.off[v] + i) + 1];
+    if (threadIdx.x < kRedBlocks) {
+      a = part2[2 * (v * kRedBlocks + threadIdx.x) + 0];
+      b = part2[2 * (v * kRedBlocks + threadIdx.x) + 1];
     }
-    sh[0][threadIdx.x] = a;
-    sh[1][threadIdx.x] = b;
-    __syncthreads();
-    for (int st = 128; st > 0; st >>= 1) {
-      if ((int)threadIdx.x < st) {
-        sh[0][threadIdx.x] += sh[0][threadIdx.x + st];
-        sh[1][threadIdx.x] += sh[1][threadIdx.x + st];
-      }
-      __syncthreads();
-    }
-    total += (1.0 - lambda) * sh[0][0] * lr.inv_count[v] +
-             lambda * (1.0 - sh[1][0] * lr.inv_count[v]);
-    __syncthreads();
+    block_sum2(a, b);
+    total += (1.0 - lambda) * a * lr.inv_count[v] + lambda * (1.0 - b * lr.inv_count[v]);
   }
   if (threadIdx.x == 0) *out = (float)(total / lr.nv);
 }
@@ -232,8 +256,9 @@ gs_status launch_loss(Ctx* ctx, const float* const* x, const float* const* y, co
   }
   gs_status st = buf_ensure(ctx, ls.gmap, sizeof(float) * 9 * max_plane);
   if (st != GS_OK) return st;
-  st = buf_ensure(ctx, ls.part, sizeof(double) * 2 * total_blocks);
+  st = buf_ensure(ctx, ls.part, sizeof(double) * 2 * (total_blocks + kRedBlocks * kMaxViews));
   if (st != GS_OK) return st;
+  double* part2 = (double*)ls.part.p + 2 * total_blocks;
   for (int v = 0; v < nv; ++v) {
     const dim3 grid((W[v] + kB - 1) / kB, (H[v] + kB - 1) / kB, 3);
     hipLaunchKernelGGL(k_ssim_fwd, grid, dim3(256), 0, s, x[v], y[v], W[v], H[v], win,
@@ -247,9 +272,12 @@ gs_status launch_loss(Ctx* ctx, const float* const* x, const float* const* y, co
     }
   }
   if (loss_out != nullptr) {
-    hipLaunchKernelGGL(k_loss_reduce, dim3(1), dim3(256), 0, s, (const double*)ls.part.p, lr,
-                       lambda, loss_out);
-    GS_LAUNCHED("loss_reduce");
+    hipLaunchKernelGGL(k_loss_partial, dim3(kRedBlocks, nv), dim3(256), 0, s,
+                       (const double*)ls.part.p, lr, part2);
+    GS_LAUNCHED("loss_partial");
+    hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(256), 0, s, (const double*)part2, lr, lambda,
+                       loss_out);
+    GS_LAUNCHED("loss_final");
   }
   return GS_OK;
 }

@@ -282,17 +282,18 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(ParamsDev prm, ViewTable
     const size_t o = (size_t)v * n + i;
     const uint2 rc = rect[o];
     if ((rc.y & 0xffffu) < (rc.x & 0xffffu)) continue;  // untouched in this view
-    float gs[9];
+    float4* a = reinterpret_cast<float4*>(acc + o * kAccStride);
+    const float4 a0 = a[0], a1 = a[1], a2 = a[2];
+    const float gs[9] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w, a2.x};
     bool nz = false;
-    for (int k = 0; k < 9; ++k) {
-      float* a = acc + ((size_t)v * 9 + k) * n + i;
-      gs[k] = *a;
-      if (gs[k] != 0.f) {
-        nz = true;
-        *a = 0.f;  // leave the accumulator cleared for the next backward pass
-      }
-    }
+#pragma unroll
+    for (int k = 0; k < 9; ++k) nz |= gs[k] != 0.f;
     if (!nz) continue;
+    // leave the accumulator cleared for the next backward pass
+    const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
+    a[0] = zero4;
+    a[1] = zero4;
+    a[2] = zero4;
     any = true;
     if (!loaded) {
       load_body(prm, i, b);

@@ -113,25 +113,48 @@ template <class F>
 __global__ __launch_bounds__(kThreads) void k_scan_down(F f, uint32_t n, const uint64_t* partial,
                                                         uint32_t* out) {
   __shared__ uint64_t sw[kWaves];
+  // striped (coalesced) loads and stores, transposed through LDS so that each
+  // thread scans kItems consecutive elements; one pad word per 32 avoids bank conflicts
+  __shared__ uint32_t buf[kChunk + kChunk / 32];
   const uint32_t base = blockIdx.x * (uint32_t)kChunk;
-  // each thread owns kItems consecutive elements
-  const uint32_t first = base + threadIdx.x * kItems;
+#pragma unroll
+  for (int j = 0; j < kItems; ++j) {
+    const uint32_t p = j * kThreads + threadIdx.x;
+    const uint32_t i = base + p;
+    buf[p + (p >> 5)] = (i < n) ? f(i) : 0u;
+  }
+  __syncthreads();
   uint32_t v[kItems];
   uint64_t s = 0;
 #pragma unroll
   for (int j = 0; j < kItems; ++j) {
-    const uint32_t i = first + j;
-    v[j] = (i < n) ? f(i) : 0u;
+    const uint32_t p = threadIdx.x * kItems + j;
+    v[j] = buf[p + (p >> 5)];
     s += v[j];
   }
   uint64_t total;
   uint64_t run = block_exclusive_scan(s, sw, total) + partial[blockIdx.x];
 #pragma unroll
   for (int j = 0; j < kItems; ++j) {
-    const uint32_t i = first + j;
-    if (i < n) out[i] = (uint32_t)run;
+    const uint32_t p = threadIdx.x * kItems + j;
+    buf[p + (p >> 5)] = (uint32_t)run;
     run += v[j];
   }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < kItems; ++j) {
+    const uint32_t p = j * kThreads + threadIdx.x;
+    const uint32_t i = base + p;
+    if (i < n) out[i] = buf[p + (p >> 5)];
+  }
+}
+
+// Tile count of every (view, Gaussian) entry in depth order (one gather).
+__global__ __launch_bounds__(256) void k_counts(const uint32_t* __restrict__ sidx,
+                                                const uint2* __restrict__ rect, uint32_t n,
+                                                uint32_t* __restrict__ counts) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) counts[i] = CountsIn{sidx, rect}(i);
 }
 
 // ---------------------------------------------------------------- radix sort
@@ -305,13 +328,16 @@ gs_status scan_tile_counts(Ctx* ctx, SortScratch& ss, const uint32_t* sidx, cons
   const uint32_t nb = nblocks_of(n);
   gs_status st = ensure_scratch(ctx, ss, nb, 0);
   if (st != GS_OK) return st;
-  CountsIn f{sidx, rect};
+  // gather the counts once (random rect reads), then scan them in place, coalesced
+  hipLaunchKernelGGL(k_counts, dim3((n + 255) / 256), dim3(256), 0, s, sidx, rect, n, offs);
+  GS_LAUNCHED("counts");
+  ArrayIn f{offs};
   auto* partial = (uint64_t*)ss.partial.p;
-  hipLaunchKernelGGL(k_scan_reduce<CountsIn>, dim3(nb), dim3(kThreads), 0, s, f, n, partial);
+  hipLaunchKernelGGL(k_scan_reduce<ArrayIn>, dim3(nb), dim3(kThreads), 0, s, f, n, partial);
   GS_LAUNCHED("scan_reduce");
   hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kThreads), 0, s, partial, nb, d_total);
   GS_LAUNCHED("scan_partials");
-  hipLaunchKernelGGL(k_scan_down<CountsIn>, dim3(nb), dim3(kThreads), 0, s, f, n, partial, offs);
+  hipLaunchKernelGGL(k_scan_down<ArrayIn>, dim3(nb), dim3(kThreads), 0, s, f, n, partial, offs);
   GS_LAUNCHED("scan_down");
   return GS_OK;
 }

@@ -81,12 +81,17 @@ typedef struct {
 
 /* Render options.  tile in {8, 16, 32} (pixels per tile side); lds_depth in
  * {32, 64, 128, 256} (Gaussians staged in LDS per batch; 0 = default 256,
- * clipped to the tile's pixel count for tile 8); bg = background colour. */
+ * clipped to the tile's pixel count for tile 8); bg = background colour;
+ * flags: GS_RENDER_PERSISTENT blends all views' tiles with one persistent
+ * launch (a resident grid draining a work queue), GS_RENDER_LONGEST_FIRST
+ * orders that queue by descending tile list length.  Results do not depend
+ * on the flags. */
+enum { GS_RENDER_PERSISTENT = 1, GS_RENDER_LONGEST_FIRST = 2 };
 typedef struct {
   int32_t tile;
   int32_t lds_depth;
   float bg[3];
-  int32_t reserved;
+  int32_t flags;
 } gs_render_opts;
 
 /* Adam hyper-parameters; learning rate per parameter group. */
@@ -232,6 +237,68 @@ gs_status gs_frame_stats_get(gs_frame* frame, gs_frame_stats* out);
 gs_status gs_frame_export(gs_frame* frame, int32_t what, int32_t view, void* dst,
                           size_t bytes, void* stream);
 void gs_frame_release(gs_frame* frame);
+
+/* ------------------------------------------------------- batched step graph
+ * One training step over n_views views (mixed sizes allowed) captured as a
+ * hipGraph: projection, sort, compositing, loss gradient, backward and (if
+ * with_adam) Adam, with no host synchronisation inside.  The paper trains on
+ * many views of one scene (Sec. III-IV); on one GPU the views of a step are
+ * rendered together instead of being spread over devices.
+ * All pointers are caller-owned device memory that must stay valid while the
+ * graph exists; the views' cameras are copied.  The record capacity is
+ * capacity_slack (>= 1.05, default 1.25) times the record count of a
+ * measuring pass run by gs_step_graph_create (which also writes the images,
+ * dl_dimg, loss and grads once, without Adam).  A replay whose records exceed
+ * the capacity sets an overflow flag and applies no Adam update;
+ * gs_step_graph_sync then reports it, grows the capacity and recaptures, and
+ * the step should be replayed (gs_step_graph_run does all of this). */
+typedef struct {
+  gs_params params;              /* read */
+  gs_params grads;               /* written (not accumulated) every step */
+  gs_params adam_m, adam_v;      /* Adam moments, updated in place */
+  const gs_camera* cams;         /* host array of n_views cameras (copied) */
+  int32_t n_views;               /* 1..16 */
+  float* const* images;          /* device [3][H][W] per view: rendered images */
+  const float* const* targets;   /* device [3][H][W] per view: training targets */
+  float* const* dl_dimg;         /* device [3][H][W] per view: image gradients */
+  float* loss;                   /* device float: the step's loss */
+  gs_render_opts render;
+  gs_adam_opts adam;
+  int32_t with_adam;
+  float lambda_dssim;
+  int64_t first_step;            /* Adam step number of the first replay (>= 1) */
+  double capacity_slack;
+} gs_step_desc;
+
+gs_status gs_step_graph_create(gs_ctx* ctx, const gs_step_desc* desc, gs_graph** out,
+                               void* stream);
+/* Enqueue one replay on `stream` (asynchronous). */
+gs_status gs_step_graph_launch(gs_graph* graph, void* stream);
+/* Wait for the last replay; report the record count and whether it overflowed
+ * (then the capacity has been grown and the graph recaptured). */
+gs_status gs_step_graph_sync(gs_graph* graph, int32_t* overflowed, int64_t* records,
+                             void* stream);
+/* Launch + sync, replaying after an overflow; synchronous. */
+gs_status gs_step_graph_run(gs_graph* graph, int64_t* records, void* stream);
+/* Capacity, last record count and the graph's frame (owned by the graph). */
+gs_status gs_step_graph_info(gs_graph* graph, int64_t* capacity, int64_t* records,
+                             gs_frame** frame);
+void gs_step_graph_destroy(gs_graph* graph);
+
+/* -------------------------------------------------------------- autotuner
+ * Times forward + backward of the given views for tile sizes {8, 16, 32},
+ * LDS depths {32, 64, 128, 256} and the grid or persistent longest-first
+ * forms, `reps` timed repetitions each after a warm-up, and returns the
+ * fastest options in *best.  table (optional, host) receives up to table_cap
+ * entries; *table_n their number.  Synchronous. */
+typedef struct {
+  int32_t tile, lds_depth, flags;
+  float ms;
+} gs_tune_entry;
+
+gs_status gs_autotune(gs_ctx* ctx, gs_params params, const gs_camera* cams, int32_t n_views,
+                      int32_t reps, gs_render_opts* best, gs_tune_entry* table,
+                      int32_t table_cap, int32_t* table_n, void* stream);
 
 #ifdef __cplusplus
 }

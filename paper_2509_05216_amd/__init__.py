@@ -7,6 +7,8 @@ from .core import (Context, Frame, Params, adam_step, bw_probe, camera, camera_f
                    camera_to_dict, init_from_points, loss_grad, orbit_cameras, render_bwd,
                    render_fwd)
 from .autograd import RasterizeFn, rasterize  # noqa: F401
+from .batched import StepGraph, autotune  # noqa: F401
+from .core import LONGEST_FIRST, PERSISTENT  # noqa: F401
 
 __all__ = ["Context", "Frame", "Params", "IsogsError", "adam_step", "camera",
            "camera_from_dict", "camera_to_dict", "init_from_points", "loss_grad", "lib",

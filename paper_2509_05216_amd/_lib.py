@@ -42,7 +42,7 @@ class GsCamera(C.Structure):
 
 class GsRenderOpts(C.Structure):
     _fields_ = [("tile", C.c_int32), ("lds_depth", C.c_int32), ("bg", C.c_float * 3),
-                ("reserved", C.c_int32)]
+                ("flags", C.c_int32)]
 
 
 class GsAdamOpts(C.Structure):
@@ -67,6 +67,20 @@ class GsFrameStats(C.Structure):
 
 _P = C.c_void_p
 _PP = C.POINTER(C.c_void_p)
+
+
+class GsStepDesc(C.Structure):
+    _fields_ = [("params", GsParams), ("grads", GsParams), ("adam_m", GsParams),
+                ("adam_v", GsParams), ("cams", C.POINTER(GsCamera)), ("n_views", C.c_int32),
+                ("images", _PP), ("targets", _PP), ("dl_dimg", _PP), ("loss", _P),
+                ("render", GsRenderOpts), ("adam", GsAdamOpts), ("with_adam", C.c_int32),
+                ("lambda_dssim", C.c_float), ("first_step", C.c_int64),
+                ("capacity_slack", C.c_double)]
+
+
+class GsTuneEntry(C.Structure):
+    _fields_ = [("tile", C.c_int32), ("lds_depth", C.c_int32), ("flags", C.c_int32),
+                ("ms", C.c_float)]
 
 # (name, restype, argtypes)
 SIGNATURES = [
@@ -94,6 +108,16 @@ SIGNATURES = [
     ("gs_frame_stats_get", C.c_int, [_P, C.POINTER(GsFrameStats)]),
     ("gs_frame_export", C.c_int, [_P, C.c_int32, C.c_int32, _P, C.c_size_t, _P]),
     ("gs_frame_release", None, [_P]),
+    ("gs_step_graph_create", C.c_int, [_P, C.POINTER(GsStepDesc), C.POINTER(_P), _P]),
+    ("gs_step_graph_launch", C.c_int, [_P, _P]),
+    ("gs_step_graph_sync", C.c_int, [_P, C.POINTER(C.c_int32), C.POINTER(C.c_int64), _P]),
+    ("gs_step_graph_run", C.c_int, [_P, C.POINTER(C.c_int64), _P]),
+    ("gs_step_graph_info", C.c_int, [_P, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
+                                     C.POINTER(_P)]),
+    ("gs_step_graph_destroy", None, [_P]),
+    ("gs_autotune", C.c_int, [_P, GsParams, C.POINTER(GsCamera), C.c_int32, C.c_int32,
+                              C.POINTER(GsRenderOpts), C.POINTER(GsTuneEntry), C.c_int32,
+                              C.POINTER(C.c_int32), _P]),
 ]
 
 _lib = None

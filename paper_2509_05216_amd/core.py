@@ -206,16 +206,20 @@ class Frame:
             pass
 
 
-def _opts(tile, lds_depth, bg):
+PERSISTENT = 1
+LONGEST_FIRST = 2
+
+
+def _opts(tile, lds_depth, bg, flags=0):
     o = L.GsRenderOpts()
-    o.tile, o.lds_depth = int(tile), int(lds_depth)
+    o.tile, o.lds_depth, o.flags = int(tile), int(lds_depth), int(flags)
     for k in range(3):
         o.bg[k] = float(bg[k])
     return o
 
 
 def render_fwd(ctx, params, cams, images=None, *, tile=16, lds_depth=256, bg=(0.0, 0.0, 0.0),
-               frame=None, stream=None):
+               flags=0, frame=None, stream=None):
     """Render len(cams) views; returns (images [list of (3, H, W) tensors], frame)."""
     dev = params.means.device
     if images is None:
@@ -227,7 +231,7 @@ def render_fwd(ctx, params, cams, images=None, *, tile=16, lds_depth=256, bg=(0.
             raise ValueError("image tensors must be contiguous float32 (3, H, W)")
     frame = frame if frame is not None else Frame()
     pa, keep = L.ptr_array([i.data_ptr() for i in images])
-    o = _opts(tile, lds_depth, bg)
+    o = _opts(tile, lds_depth, bg, flags)
     L.check(L.lib().gs_render_fwd(ctx.handle, params.abi(), _cam_array(cams), len(cams), pa,
                                   C.byref(o), C.byref(frame.handle), _stream(stream)))
     return images, frame

@@ -26,18 +26,24 @@ struct AdamSegs {
   int nseg;
   float b1, b2, eps, inv_bc1, inv_sqrt_bc2;
   int zero_grads;
+  const float* dev_bc;    // optional: bias corrections read from the device (graph steps)
+  const uint32_t* skip;   // optional: no update while *skip != 0 (record overflow)
 };
 
-__device__ inline void adam1(float& p, float& g, float& m, float& v, float lr, const AdamSegs& a) {
+__device__ inline void adam1(float& p, float& g, float& m, float& v, float lr, float inv_bc1,
+                             float inv_sqrt_bc2, const AdamSegs& a) {
   m = a.b1 * m + (1.f - a.b1) * g;
   v = a.b2 * v + (1.f - a.b2) * g * g;
-  const float mh = m * a.inv_bc1;
-  const float denom = sqrtf(v) * a.inv_sqrt_bc2 + a.eps;
+  const float mh = m * inv_bc1;
+  const float denom = sqrtf(v) * inv_sqrt_bc2 + a.eps;
   p -= lr * mh / denom;
   if (a.zero_grads) g = 0.f;
 }
 
 __global__ __launch_bounds__(kThreads) void k_adam(AdamSegs a) {
+  if (a.skip != nullptr && *a.skip != 0u) return;
+  const float inv_bc1 = a.dev_bc != nullptr ? a.dev_bc[0] : a.inv_bc1;
+  const float inv_sqrt_bc2 = a.dev_bc != nullptr ? a.dev_bc[1] : a.inv_sqrt_bc2;
   int s = 0;
   while (s + 1 < a.nseg && blockIdx.x >= a.block_start[s + 1]) ++s;
   const long long first = ((long long)(blockIdx.x - a.block_start[s]) * kPerBlock) + threadIdx.x * 4;
@@ -52,10 +58,10 @@ __global__ __launch_bounds__(kThreads) void k_adam(AdamSegs a) {
   if (aligned && first + 4 <= n) {
     float4 p = *(float4*)(P + first), g = *(float4*)(G + first);
     float4 m = *(float4*)(M + first), v = *(float4*)(V + first);
-    adam1(p.x, g.x, m.x, v.x, lr, a);
-    adam1(p.y, g.y, m.y, v.y, lr, a);
-    adam1(p.z, g.z, m.z, v.z, lr, a);
-    adam1(p.w, g.w, m.w, v.w, lr, a);
+    adam1(p.x, g.x, m.x, v.x, lr, inv_bc1, inv_sqrt_bc2, a);
+    adam1(p.y, g.y, m.y, v.y, lr, inv_bc1, inv_sqrt_bc2, a);
+    adam1(p.z, g.z, m.z, v.z, lr, inv_bc1, inv_sqrt_bc2, a);
+    adam1(p.w, g.w, m.w, v.w, lr, inv_bc1, inv_sqrt_bc2, a);
     *(float4*)(P + first) = p;
     *(float4*)(M + first) = m;
     *(float4*)(V + first) = v;
@@ -63,7 +69,7 @@ __global__ __launch_bounds__(kThreads) void k_adam(AdamSegs a) {
   } else {
     for (long long i = first; i < n && i < first + 4; ++i) {
       float p = P[i], g = G[i], m = M[i], v = V[i];
-      adam1(p, g, m, v, lr, a);
+      adam1(p, g, m, v, lr, inv_bc1, inv_sqrt_bc2, a);
       P[i] = p;
       M[i] = m;
       V[i] = v;
@@ -75,7 +81,8 @@ __global__ __launch_bounds__(kThreads) void k_adam(AdamSegs a) {
 }  // namespace
 
 gs_status launch_adam(const gs_params& p, const gs_params& g, const gs_params& m,
-                      const gs_params& v, const gs_adam_opts& o, int64_t step, hipStream_t s) {
+                      const gs_params& v, const gs_adam_opts& o, int64_t step, hipStream_t s,
+                      const float* dev_bc, const uint32_t* skip) {
   const long long n = p.n;
   const int nb = (p.sh_degree + 1) * (p.sh_degree + 1);
   AdamSegs a;
@@ -113,6 +120,8 @@ gs_status launch_adam(const gs_params& p, const gs_params& g, const gs_params& m
   a.inv_bc1 = (float)(1.0 / (1.0 - pow((double)o.beta1, (double)step)));
   a.inv_sqrt_bc2 = (float)(1.0 / sqrt(1.0 - pow((double)o.beta2, (double)step)));
   a.zero_grads = o.zero_grads;
+  a.dev_bc = dev_bc;
+  a.skip = skip;
   hipLaunchKernelGGL(k_adam, dim3(blocks), dim3(kThreads), 0, s, a);
   GS_LAUNCHED("adam");
   return GS_OK;

@@ -25,6 +25,11 @@ gs_status hip_fail(hipError_t e, const char* what) {
 
 gs_status buf_ensure(Ctx* ctx, DevBuf& b, size_t bytes) {
   if (bytes <= b.cap) return GS_OK;
+  if (ctx->capturing) {
+    set_error("internal: a buffer would grow (%zu -> %zu bytes) during graph capture", b.cap,
+              bytes);
+    return GS_ERR_CAPACITY;
+  }
   size_t want = bytes + bytes / 8;
   want = (want + 4095) & ~(size_t)4095;
   const size_t after = ctx->in_use - b.cap + want;
@@ -82,7 +87,7 @@ static void give_event(Ctx* c, hipEvent_t e) {
 }
 
 StageTimer::StageTimer(Ctx* c_, int st, hipStream_t s_) : c(c_), stage(st), s(s_) {
-  if (c == nullptr || !c->timing) return;
+  if (c == nullptr || !c->timing || c->capturing) return;
   a = take_event(c);
   if (a != nullptr && hipEventRecord(a, s) != hipSuccess) {
     give_event(c, a);
@@ -132,16 +137,18 @@ size_t Frame::bytes() const {
   size_t s = splat.cap + rect.cap + dkey.cap + dkw[0].cap + dkw[1].cap + sidx[0].cap +
              sidx[1].cap + clampm.cap + offs.cap + tkey[0].cap + tkey[1].cap + tval[0].cap +
              tval[1].cap + ranges.cap + finalT.cap + ncon.cap + acc.cap + ss.hist.cap +
-             ss.partial.cap + ss.total.cap;
+             ss.partial.cap + ss.total.cap + words.cap + okey[0].cap + okey[1].cap +
+             oval[0].cap + oval[1].cap;
   return s;
 }
 
 static void frame_free(Frame* f) {
   Ctx* c = f->ctx;
-  DevBuf* all[] = {&f->splat,   &f->rect,    &f->dkey,    &f->dkw[0],  &f->dkw[1],
-                   &f->sidx[0], &f->sidx[1], &f->clampm,  &f->offs,    &f->tkey[0],
-                   &f->tkey[1], &f->tval[0], &f->tval[1], &f->ranges,  &f->finalT,
-                   &f->ncon,    &f->acc,     &f->ss.hist, &f->ss.partial, &f->ss.total};
+  DevBuf* all[] = {&f->splat,   &f->rect,    &f->dkey,    &f->dkw[0],     &f->dkw[1],
+                   &f->sidx[0], &f->sidx[1], &f->clampm,  &f->offs,       &f->tkey[0],
+                   &f->tkey[1], &f->tval[0], &f->tval[1], &f->ranges,     &f->finalT,
+                   &f->ncon,    &f->acc,     &f->ss.hist, &f->ss.partial, &f->ss.total,
+                   &f->words,   &f->okey[0], &f->okey[1], &f->oval[0],    &f->oval[1]};
   for (DevBuf* b : all) buf_free(c, *b);
   if (f->pinned != nullptr) (void)hipHostFree(f->pinned);
   f->pinned = nullptr;
@@ -176,7 +183,18 @@ static bool valid_camera(const gs_camera& c, int v) {
   return true;
 }
 
-static ParamsDev params_dev(const gs_params& p) {
+GradsDev grads_dev(const gs_params& g, int accumulate) {
+  GradsDev d;
+  d.means = g.means;
+  d.log_scales = g.log_scales;
+  d.quats = g.quats;
+  d.logits = g.opacity_logits;
+  d.sh = g.sh;
+  d.accumulate = accumulate;
+  return d;
+}
+
+ParamsDev params_dev(const gs_params& p) {
   ParamsDev d;
   d.means = p.means;
   d.log_scales = p.log_scales;
@@ -260,6 +278,12 @@ static gs_status frame_buffers(Frame& f) {
     f.acc_zeroed = false;
   }
 #undef ENS
+  if (f.words.cap == 0) {
+    st = buf_ensure(c, f.words, kWordCount * 4);
+    if (st != GS_OK) return st;
+    st = launch_fill_u32(f.words.p, 0u, kWordCount, nullptr);
+    if (st != GS_OK) return st;
+  }
   if (f.pinned == nullptr) GS_HIP(hipHostMalloc((void**)&f.pinned, 64, hipHostMallocDefault));
   return GS_OK;
 }
@@ -456,12 +480,17 @@ gs_status gs_render_fwd(gs_ctx* ctx, gs_params params, const gs_camera* cams, in
     set_error("gs_render_fwd: n_views * n exceeds 2^32 - 1");
     return GS_ERR_CAPACITY;
   }
-  int tile = 16, depth = 256;
+  int tile = 16, depth = 256, flags = 0;
   float bg[3] = {0.f, 0.f, 0.f};
   if (opts != nullptr) {
     tile = opts->tile;
     depth = opts->lds_depth == 0 ? 256 : opts->lds_depth;
+    flags = opts->flags;
     for (int k = 0; k < 3; ++k) bg[k] = opts->bg[k];
+  }
+  if ((flags & ~(GS_RENDER_PERSISTENT | GS_RENDER_LONGEST_FIRST)) != 0) {
+    set_error("gs_render_fwd: unknown render flags 0x%x", flags);
+    return GS_ERR_INVALID;
   }
   if (tile != 8 && tile != 16 && tile != 32) {
     set_error("gs_render_fwd: tile %d not in {8, 16, 32}", tile);
@@ -494,6 +523,9 @@ gs_status gs_render_fwd(gs_ctx* ctx, gs_params params, const gs_camera* cams, in
   f.views = n_views;
   f.tile = tile;
   f.depth = depth;
+  f.persistent = (flags & GS_RENDER_PERSISTENT) != 0;
+  f.lpt = f.persistent && (flags & GS_RENDER_LONGEST_FIRST) != 0;
+  f.tile_order = nullptr;
   f.sh_degree = params.sh_degree;
   f.K = 0;
   st = build_views(f, cams, n_views, images, bg);
@@ -511,7 +543,19 @@ gs_status gs_render_fwd(gs_ctx* ctx, gs_params params, const gs_camera* cams, in
     f.acc_zeroed = true;
   }
   *state = fr;
-  const ParamsDev pd = params_dev(params);
+  return forward_stages(ctx, f, params_dev(params), s, 0);
+}
+
+}  // extern "C"
+
+namespace isogs {
+
+// The forward pipeline.  cap == 0: the record count K is read back to the host
+// and the record buffers sized to it (one stream synchronisation).  cap > 0:
+// no host synchronisation — K stays on the device (clamped to cap, with the
+// overflow word set when the records do not fit), as a captured graph needs.
+gs_status forward_stages(Ctx* ctx, Frame& f, const ParamsDev& pd, hipStream_t s, uint32_t cap) {
+  gs_status st = GS_OK;
   const uint32_t vn = (uint32_t)((size_t)f.views * (size_t)f.n);
 
   // 1. projection + SH
@@ -531,52 +575,89 @@ gs_status gs_render_fwd(gs_ctx* ctx, gs_params params, const gs_camera* cams, in
   if (st != GS_OK) return st;
   f.sidx_sel = in_b;
   const uint32_t* sidx = (const uint32_t*)f.sidx[in_b].p;
-  // 3. record offsets and the total K (read back to size the record buffers)
-  st = buf_ensure(ctx, f.ss.total, 16);
-  if (st != GS_OK) return st;
+  // 3. record offsets and the total K
+  uint32_t* words = (uint32_t*)f.words.p;
+  uint64_t* d_total = (uint64_t*)(words + kWordTotal);
   {
     StageTimer tm(ctx, ST_SCAN, s);
     st = scan_tile_counts(ctx, f.ss, sidx, (const uint2*)f.rect.p, vn, (uint32_t*)f.offs.p,
-                          (uint64_t*)f.ss.total.p, s);
+                          d_total, s);
   }
   if (st != GS_OK) return st;
-  GS_HIP(hipMemcpyAsync(f.pinned, f.ss.total.p, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
-  GS_HIP(hipStreamSynchronize(s));
-  const uint64_t K = f.pinned[0];
-  if (K >= 0xffffffffULL) {
-    set_error("gs_render_fwd: %llu (Gaussian, tile) records exceed 2^32 - 1",
-              (unsigned long long)K);
-    return GS_ERR_CAPACITY;
-  }
-  f.K = (int64_t)K;
-  for (int k = 0; k < 2; ++k) {
-    st = buf_ensure(ctx, f.tkey[k], (size_t)(K + 1) * 4);
-    if (st == GS_OK) st = buf_ensure(ctx, f.tval[k], (size_t)(K + 1) * 4);
+  uint32_t n_rec = 0;              // host bound on the record count (grid sizes)
+  const uint32_t* d_K = nullptr;   // device record count (device-count pipelines)
+  uint32_t* overflow = nullptr;
+  if (cap == 0) {
+    GS_HIP(hipMemcpyAsync(f.pinned, d_total, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+    GS_HIP(hipStreamSynchronize(s));
+    const uint64_t K = f.pinned[0];
+    if (K >= 0xffffffffULL) {
+      set_error("gs_render_fwd: %llu (Gaussian, tile) records exceed 2^32 - 1",
+                (unsigned long long)K);
+      return GS_ERR_CAPACITY;
+    }
+    f.K = (int64_t)K;
+    n_rec = (uint32_t)K;
+    for (int k = 0; k < 2; ++k) {
+      st = buf_ensure(ctx, f.tkey[k], (size_t)(K + 1) * 4);
+      if (st == GS_OK) st = buf_ensure(ctx, f.tval[k], (size_t)(K + 1) * 4);
+      if (st != GS_OK) return st;
+    }
+  } else {
+    f.K = cap;
+    n_rec = cap;
+    d_K = words + kWordK;
+    overflow = words + kWordOverflow;
+    st = launch_clamp_count(d_total, cap, words + kWordK, overflow, s);
     if (st != GS_OK) return st;
   }
   // 4. records in depth order, then the stable sort on the tile digits
   {
     StageTimer tm(ctx, ST_EMIT, s);
-    st = launch_emit(f.vt, f, sidx, vn, s);
+    st = launch_emit(f.vt, f, sidx, vn, overflow, s);
   }
   if (st != GS_OK) return st;
   {
     StageTimer tm(ctx, ST_TILE_SORT, s);
     st = sort_pairs_u32(ctx, f.ss, (const uint32_t*)f.tkey[0].p, (const uint32_t*)f.tval[0].p,
                         (uint32_t*)f.tkey[1].p, (uint32_t*)f.tval[1].p, (uint32_t*)f.tkey[0].p,
-                        (uint32_t*)f.tval[0].p, (uint32_t)K, nullptr, f.key_bits, &in_b, s);
+                        (uint32_t*)f.tval[0].p, n_rec, d_K, f.key_bits, &in_b, s);
   }
   if (st != GS_OK) return st;
-  f.tkey_sel = (K == 0) ? 0 : (in_b ? 0 : 1);
+  f.tkey_sel = (n_rec == 0) ? 0 : (in_b ? 0 : 1);
   // 5. per-tile ranges, 6. compositing
   {
     StageTimer tm(ctx, ST_RANGES, s);
-    st = launch_ranges(f, s);
+    st = launch_ranges(f, n_rec, d_K, s);
+    if (st == GS_OK && f.lpt) st = launch_tile_order(f, s);
+    // persistent work queues start empty
+    if (st == GS_OK && f.persistent) st = launch_fill_u32(f.words.p, 0u, 2, s);
   }
   if (st != GS_OK) return st;
   StageTimer tm(ctx, ST_BLEND_FWD, s);
   return launch_blend_fwd(f.vt, f, s);
 }
+
+// The backward pipeline: reverse traversal, then the chain rule to the parameters.
+gs_status backward_stages(Ctx* ctx, Frame& f, const ParamsDev& pd, const GradsDev& g,
+                          hipStream_t s) {
+  gs_status st = GS_OK;
+  if (f.K > 0) {
+    if (f.persistent) {
+      st = launch_fill_u32((uint32_t*)f.words.p + kWordBwdCounter, 0u, 1, s);
+      if (st != GS_OK) return st;
+    }
+    StageTimer tm(ctx, ST_BLEND_BWD, s);
+    st = launch_blend_bwd(f.vt, f, s);
+  }
+  if (st != GS_OK) return st;
+  StageTimer tm(ctx, ST_PROJECT_BWD, s);
+  return launch_preprocess_bwd(pd, f.vt, f, g, s);
+}
+
+}  // namespace isogs
+
+extern "C" {
 
 gs_status gs_loss_grad(gs_ctx* ctx, const float* const* rendered, const float* const* target,
                        const gs_camera* cams, int32_t n_views, float lambda_dssim,
@@ -640,20 +721,7 @@ gs_status gs_render_bwd(gs_ctx* ctx, gs_frame* frame, gs_params params,
   gs_status st = set_device(ctx);
   if (st != GS_OK) return st;
   hipStream_t s = (hipStream_t)stream;
-  if (f.K > 0) {
-    StageTimer tm(ctx, ST_BLEND_BWD, s);
-    st = launch_blend_bwd(f.vt, f, s);
-  }
-  if (st != GS_OK) return st;
-  GradsDev g;
-  g.means = grads.means;
-  g.log_scales = grads.log_scales;
-  g.quats = grads.quats;
-  g.logits = grads.opacity_logits;
-  g.sh = grads.sh;
-  g.accumulate = accumulate;
-  StageTimer tm(ctx, ST_PROJECT_BWD, s);
-  return launch_preprocess_bwd(params_dev(params), f.vt, f, g, s);
+  return backward_stages(ctx, f, params_dev(params), grads_dev(grads, accumulate), s);
 }
 
 gs_status gs_adam_step(gs_ctx* ctx, gs_params p, gs_params g, gs_params m, gs_params v,

@@ -143,16 +143,14 @@ struct Layout {
   }
 };
 
+// Forward of one tile (global tile id gt) by the whole workgroup.
 template <int TILE, int DEPTH>
-__global__ __launch_bounds__(TILE* TILE) void k_blend_fwd(ViewTable vt,
-                                                          const uint2* __restrict__ ranges,
-                                                          const uint32_t* __restrict__ tval,
-                                                          const float4* __restrict__ splat,
-                                                          float* __restrict__ finalT,
-                                                          uint32_t* __restrict__ ncon) {
+__device__ inline void fwd_tile(Stage<TILE * TILE, DEPTH>& st, const ViewTable& vt, int gt,
+                                const uint2* __restrict__ ranges,
+                                const uint32_t* __restrict__ tval,
+                                const float4* __restrict__ splat, float* __restrict__ finalT,
+                                uint32_t* __restrict__ ncon) {
   constexpr int NT = TILE * TILE;
-  __shared__ Stage<NT, DEPTH> st;
-  const int gt = blockIdx.x;
   const int v = view_of_tile(vt, gt);
   const CamDev& cam = vt.v[v];
   const int lt = gt - cam.tile_offset;
@@ -203,6 +201,46 @@ __global__ __launch_bounds__(TILE* TILE) void k_blend_fwd(ViewTable vt,
     cam.image[2 * plane + pix] = cb + T * vt.bg[2];
     finalT[cam.pix_offset + pix] = T;
     ncon[cam.pix_offset + pix] = last;
+  }
+}
+
+// One workgroup per tile.
+template <int TILE, int DEPTH>
+__global__ __launch_bounds__(TILE* TILE) void k_blend_fwd(ViewTable vt,
+                                                          const uint2* __restrict__ ranges,
+                                                          const uint32_t* __restrict__ tval,
+                                                          const float4* __restrict__ splat,
+                                                          float* __restrict__ finalT,
+                                                          uint32_t* __restrict__ ncon) {
+  __shared__ Stage<TILE * TILE, DEPTH> st;
+  fwd_tile<TILE, DEPTH>(st, vt, blockIdx.x, ranges, tval, splat, finalT, ncon);
+}
+
+// Next work item of a persistent workgroup: a tile index from the shared
+// counter, mapped through the tile order when one is given; -1 when drained.
+__device__ inline int next_tile(uint32_t* counter, const uint32_t* order, int total,
+                                uint32_t* slot) {
+  __syncthreads();  // the previous item (and its LDS use) is finished
+  if (threadIdx.x == 0) *slot = atomicAdd(counter, 1u);
+  __syncthreads();
+  const uint32_t it = *slot;
+  if (it >= (uint32_t)total) return -1;
+  return order != nullptr ? (int)order[it] : (int)it;
+}
+
+// Persistent form: a grid sized to the device's resident capacity drains the
+// (view, tile) work queue of all views, in the given tile order.
+template <int TILE, int DEPTH>
+__global__ __launch_bounds__(TILE* TILE) void k_blend_fwd_persistent(
+    ViewTable vt, const uint2* __restrict__ ranges, const uint32_t* __restrict__ tval,
+    const float4* __restrict__ splat, float* __restrict__ finalT, uint32_t* __restrict__ ncon,
+    const uint32_t* __restrict__ order, uint32_t* counter) {
+  __shared__ Stage<TILE * TILE, DEPTH> st;
+  __shared__ uint32_t slot;
+  for (;;) {
+    const int gt = next_tile(counter, order, vt.total_tiles, &slot);
+    if (gt < 0) break;
+    fwd_tile<TILE, DEPTH>(st, vt, gt, ranges, tval, splat, finalT, ncon);
   }
 }
 
@@ -266,19 +304,25 @@ __device__ inline void wave_reduce_add(const float* g, float* part) {
 }
 
 template <int TILE, int DEPTH>
-__global__ __launch_bounds__(TILE* TILE) void k_blend_bwd(ViewTable vt, int n_gauss,
-                                                          const uint2* __restrict__ ranges,
-                                                          const uint32_t* __restrict__ tval,
-                                                          const float4* __restrict__ splat,
-                                                          const float* __restrict__ finalT,
-                                                          const uint32_t* __restrict__ ncon,
-                                                          float* __restrict__ acc) {
+struct BwdSmem {
+  Stage<TILE * TILE, DEPTH> st;
+  float part[DEPTH * 9];
+  uint32_t smax[TILE * TILE / 64];
+};
+
+// Backward of one tile (global tile id gt) by the whole workgroup.
+template <int TILE, int DEPTH>
+__device__ inline void bwd_tile(BwdSmem<TILE, DEPTH>& sm, const ViewTable& vt, int gt,
+                                const uint2* __restrict__ ranges,
+                                const uint32_t* __restrict__ tval,
+                                const float4* __restrict__ splat,
+                                const float* __restrict__ finalT,
+                                const uint32_t* __restrict__ ncon, float* __restrict__ acc) {
   constexpr int NT = TILE * TILE;
   constexpr int NW = NT / 64;
-  __shared__ Stage<NT, DEPTH> st;
-  __shared__ float part[DEPTH * 9];
-  __shared__ uint32_t smax[NW];
-  const int gt = blockIdx.x;
+  Stage<NT, DEPTH>& st = sm.st;
+  float* part = sm.part;
+  uint32_t* smax = sm.smax;
   const int v = view_of_tile(vt, gt);
   const CamDev& cam = vt.v[v];
   const int lt = gt - cam.tile_offset;
@@ -379,7 +423,54 @@ __global__ __launch_bounds__(TILE* TILE) void k_blend_bwd(ViewTable vt, int n_ga
 }
 
 template <int TILE, int DEPTH>
+__global__ __launch_bounds__(TILE* TILE) void k_blend_bwd(ViewTable vt,
+                                                          const uint2* __restrict__ ranges,
+                                                          const uint32_t* __restrict__ tval,
+                                                          const float4* __restrict__ splat,
+                                                          const float* __restrict__ finalT,
+                                                          const uint32_t* __restrict__ ncon,
+                                                          float* __restrict__ acc) {
+  __shared__ BwdSmem<TILE, DEPTH> sm;
+  bwd_tile<TILE, DEPTH>(sm, vt, blockIdx.x, ranges, tval, splat, finalT, ncon, acc);
+}
+
+template <int TILE, int DEPTH>
+__global__ __launch_bounds__(TILE* TILE) void k_blend_bwd_persistent(
+    ViewTable vt, const uint2* __restrict__ ranges, const uint32_t* __restrict__ tval,
+    const float4* __restrict__ splat, const float* __restrict__ finalT,
+    const uint32_t* __restrict__ ncon, float* __restrict__ acc, const uint32_t* __restrict__ order,
+    uint32_t* counter) {
+  __shared__ BwdSmem<TILE, DEPTH> sm;
+  __shared__ uint32_t slot;
+  for (;;) {
+    const int gt = next_tile(counter, order, vt.total_tiles, &slot);
+    if (gt < 0) break;
+    bwd_tile<TILE, DEPTH>(sm, vt, gt, ranges, tval, splat, finalT, ncon, acc);
+  }
+}
+
+// Workgroups of a persistent kernel that are resident at once on the device.
+template <class K>
+int resident_grid(K kernel, int threads, const Ctx* ctx) {
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess ||
+      per_cu < 1)
+    per_cu = 1;
+  return per_cu * ctx->cu_count;
+}
+
+template <int TILE, int DEPTH>
 gs_status fwd_t(const ViewTable& vt, Frame& f, hipStream_t s) {
+  if (f.persistent) {
+    auto kern = k_blend_fwd_persistent<TILE, DEPTH>;
+    const int grid = std::min(resident_grid(kern, TILE * TILE, f.ctx), vt.total_tiles);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(TILE * TILE), 0, s, vt, (const uint2*)f.ranges.p,
+                       (const uint32_t*)f.tval[f.tkey_sel].p, (const float4*)f.splat.p,
+                       (float*)f.finalT.p, (uint32_t*)f.ncon.p, f.tile_order,
+                       (uint32_t*)f.words.p + kWordFwdCounter);
+    GS_LAUNCHED("blend_fwd_persistent");
+    return GS_OK;
+  }
   hipLaunchKernelGGL((k_blend_fwd<TILE, DEPTH>), dim3(vt.total_tiles), dim3(TILE * TILE), 0, s,
                      vt, (const uint2*)f.ranges.p, (const uint32_t*)f.tval[f.tkey_sel].p,
                      (const float4*)f.splat.p, (float*)f.finalT.p, (uint32_t*)f.ncon.p);
@@ -389,10 +480,20 @@ gs_status fwd_t(const ViewTable& vt, Frame& f, hipStream_t s) {
 
 template <int TILE, int DEPTH>
 gs_status bwd_t(const ViewTable& vt, Frame& f, hipStream_t s) {
+  if (f.persistent) {
+    auto kern = k_blend_bwd_persistent<TILE, DEPTH>;
+    const int grid = std::min(resident_grid(kern, TILE * TILE, f.ctx), vt.total_tiles);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(TILE * TILE), 0, s, vt, (const uint2*)f.ranges.p,
+                       (const uint32_t*)f.tval[f.tkey_sel].p, (const float4*)f.splat.p,
+                       (const float*)f.finalT.p, (const uint32_t*)f.ncon.p, (float*)f.acc.p,
+                       f.tile_order, (uint32_t*)f.words.p + kWordBwdCounter);
+    GS_LAUNCHED("blend_bwd_persistent");
+    return GS_OK;
+  }
   hipLaunchKernelGGL((k_blend_bwd<TILE, DEPTH>), dim3(vt.total_tiles), dim3(TILE * TILE), 0, s,
-                     vt, (int)f.n, (const uint2*)f.ranges.p,
-                     (const uint32_t*)f.tval[f.tkey_sel].p, (const float4*)f.splat.p,
-                     (const float*)f.finalT.p, (const uint32_t*)f.ncon.p, (float*)f.acc.p);
+                     vt, (const uint2*)f.ranges.p, (const uint32_t*)f.tval[f.tkey_sel].p,
+                     (const float4*)f.splat.p, (const float*)f.finalT.p,
+                     (const uint32_t*)f.ncon.p, (float*)f.acc.p);
   GS_LAUNCHED("blend_bwd");
   return GS_OK;
 }

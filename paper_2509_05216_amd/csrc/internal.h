@@ -31,6 +31,18 @@ constexpr int kMaxViews = 16;
 // one record per (view, Gaussian), 16-byte aligned.
 constexpr int kAccStride = 12;
 
+// Frame-owned device words (u32 slots; 64-bit values at even slots).
+enum Word {
+  kWordFwdCounter = 0,  // work counter of the persistent forward blend
+  kWordBwdCounter = 1,  // work counter of the persistent backward blend
+  kWordK = 2,           // record count clamped to the capacity (device-count pipelines)
+  kWordOverflow = 3,    // set when the records exceed the capacity
+  kWordBC = 4,          // two floats: Adam 1/(1 - b1^t), 1/sqrt(1 - b2^t)
+  kWordStep = 6,        // int64: Adam step of the next graph launch
+  kWordTotal = 8,       // u64: record count from the scan
+  kWordCount = 16
+};
+
 struct CamDev {
   float R[9];
   float t[3];
@@ -126,6 +138,8 @@ struct Ctx {
   int cu_count = 0;
   hipDeviceProp_t prop;
   void* loss_scratch = nullptr;  // loss.hip workspace (g maps, block partials)
+  // set while a graph is being captured: no allocation, no stage events
+  bool capturing = false;
   // stage timing
   bool timing = false;
   PendingTiming* pending = nullptr;
@@ -173,10 +187,22 @@ struct Frame {
   int tkey_sel = 0;  // which of tkey/tval holds the sorted records
   int sidx_sel = 0;  // which of sidx holds the depth-sorted (view, Gaussian) indices
   bool acc_zeroed = false;
+  bool persistent = false;            // blend with persistent work-queue kernels
+  bool lpt = false;                   // persistent queue in longest-list-first tile order
+  const uint32_t* tile_order = nullptr;
+  DevBuf words;                       // kWordCount device words
+  DevBuf okey[2], oval[2];            // tile-order sort buffers
   SortScratch ss;
   uint64_t* pinned = nullptr;  // host-pinned readback word
   size_t bytes() const;
 };
+
+// ------------------------------------------------------------- pipelines (api.hip)
+ParamsDev params_dev(const gs_params& p);
+GradsDev grads_dev(const gs_params& g, int accumulate);
+gs_status forward_stages(Ctx* ctx, Frame& f, const ParamsDev& pd, hipStream_t s, uint32_t cap);
+gs_status backward_stages(Ctx* ctx, Frame& f, const ParamsDev& pd, const GradsDev& g,
+                          hipStream_t s);
 
 // ----------------------------------------------------------- kernel hosts
 // preprocess.hip
@@ -195,9 +221,19 @@ gs_status sort_pairs_u32(Ctx* ctx, SortScratch& ss, const uint32_t* kin, const u
                          const uint32_t* d_n, int bits, int* result_in_b, hipStream_t s);
 gs_status scan_tile_counts(Ctx* ctx, SortScratch& ss, const uint32_t* sidx, const uint2* rect,
                            uint32_t n, uint32_t* offs, uint64_t* d_total, hipStream_t s);
+// Scratch for sorts of up to n pairs (so that no allocation happens later, e.g. in capture).
+gs_status sort_reserve(Ctx* ctx, SortScratch& ss, uint32_t n);
+// K = min(*total, cap); *overflow |= (*total > cap).
+gs_status launch_clamp_count(const uint64_t* total, uint32_t cap, uint32_t* K,
+                             uint32_t* overflow, hipStream_t s);
+// Records of count (view, Gaussian) entries; overflow (optional) is set, and the
+// entry skipped, when its records would pass the record buffers' capacity.
 gs_status launch_emit(const ViewTable& vt, Frame& f, const uint32_t* sidx, uint32_t count,
-                      hipStream_t s);
-gs_status launch_ranges(Frame& f, hipStream_t s);
+                      uint32_t* overflow, hipStream_t s);
+// Per-tile ranges of n_rec records (d_K: device count bounding n_rec, optional).
+gs_status launch_ranges(Frame& f, uint32_t n_rec, const uint32_t* d_K, hipStream_t s);
+// Tiles in descending list length (ties by tile id) for the persistent queue.
+gs_status launch_tile_order(Frame& f, hipStream_t s);
 gs_status launch_fill_u32(void* p, uint32_t value, size_t count, hipStream_t s);
 gs_status launch_export_keys(Frame& f, uint64_t* dst, hipStream_t s);
 // blend.hip
@@ -210,8 +246,11 @@ gs_status launch_loss(Ctx* ctx, const float* const* x, const float* const* y, co
 // probe.hip
 gs_status launch_copy_probe(Ctx* ctx, const void* src, void* dst, size_t bytes, hipStream_t s);
 // adam.hip
+// dev_bc (optional): device {1/(1-b1^t), 1/sqrt(1-b2^t)} replacing the host values of
+// `step`; skip (optional): device flag that suppresses the update while nonzero.
 gs_status launch_adam(const gs_params& p, const gs_params& g, const gs_params& m,
-                      const gs_params& v, const gs_adam_opts& o, int64_t step, hipStream_t s);
+                      const gs_params& v, const gs_adam_opts& o, int64_t step, hipStream_t s,
+                      const float* dev_bc = nullptr, const uint32_t* skip = nullptr);
 
 }  // namespace isogs
 

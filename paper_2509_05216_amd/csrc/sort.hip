@@ -292,6 +292,23 @@ __global__ __launch_bounds__(256) void k_fill_u32(uint32_t* p, uint32_t value, s
     p[i] = value;
 }
 
+__global__ void k_clamp_count(const uint64_t* __restrict__ total, uint32_t cap,
+                              uint32_t* __restrict__ K, uint32_t* __restrict__ overflow) {
+  const uint64_t t = *total;
+  *K = t < cap ? (uint32_t)t : cap;
+  if (t > cap) *overflow = 1u;
+}
+
+// Sort key of a tile for the longest-first work queue: 2^20 - 1 - min(length, 2^20 - 1).
+__global__ __launch_bounds__(256) void k_tile_len_keys(const uint2* __restrict__ ranges,
+                                                       uint32_t tiles, uint32_t* __restrict__ key) {
+  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= tiles) return;
+  const uint2 r = ranges[t];
+  const uint32_t len = r.y - r.x;
+  key[t] = 0xFFFFFu - (len < 0xFFFFFu ? len : 0xFFFFFu);
+}
+
 __global__ __launch_bounds__(256) void k_export_keys(const uint32_t* __restrict__ tkey,
                                                      const uint32_t* __restrict__ tval,
                                                      const uint32_t* __restrict__ dkey, uint32_t K,
@@ -383,25 +400,59 @@ gs_status sort_pairs_u32(Ctx* ctx, SortScratch& ss, const uint32_t* kin, const u
 }
 
 gs_status launch_emit(const ViewTable& vt, Frame& f, const uint32_t* sidx, uint32_t count,
-                      hipStream_t s) {
+                      uint32_t* overflow, hipStream_t s) {
   if (count == 0) return GS_OK;
   const size_t cap_bytes = f.tkey[0].cap < f.tval[0].cap ? f.tkey[0].cap : f.tval[0].cap;
   const uint32_t cap = (uint32_t)(cap_bytes / sizeof(uint32_t));
   hipLaunchKernelGGL(k_emit, dim3((count + 255) / 256), dim3(256), 0, s, vt, (int)f.n, sidx,
                      (const uint2*)f.rect.p, (const uint32_t*)f.offs.p, count, cap,
-                     (uint32_t*)f.tkey[0].p, (uint32_t*)f.tval[0].p, (uint32_t*)nullptr);
+                     (uint32_t*)f.tkey[0].p, (uint32_t*)f.tval[0].p, overflow);
   GS_LAUNCHED("emit");
   return GS_OK;
 }
 
-gs_status launch_ranges(Frame& f, hipStream_t s) {
+gs_status launch_ranges(Frame& f, uint32_t n_rec, const uint32_t* d_K, hipStream_t s) {
   gs_status st = launch_fill_u32(f.ranges.p, 0u, (size_t)f.vt.total_tiles * 2, s);
   if (st != GS_OK) return st;
-  if (f.K == 0) return GS_OK;
-  hipLaunchKernelGGL(k_ranges, dim3((unsigned)((f.K + 255) / 256)), dim3(256), 0, s,
-                     (const uint32_t*)f.tkey[f.tkey_sel].p, (uint32_t)f.K,
-                     (const uint32_t*)nullptr, (uint2*)f.ranges.p);
+  if (n_rec == 0) return GS_OK;
+  hipLaunchKernelGGL(k_ranges, dim3((n_rec + 255) / 256), dim3(256), 0, s,
+                     (const uint32_t*)f.tkey[f.tkey_sel].p, n_rec, d_K, (uint2*)f.ranges.p);
   GS_LAUNCHED("ranges");
+  return GS_OK;
+}
+
+gs_status launch_clamp_count(const uint64_t* total, uint32_t cap, uint32_t* K,
+                             uint32_t* overflow, hipStream_t s) {
+  hipLaunchKernelGGL(k_clamp_count, dim3(1), dim3(1), 0, s, total, cap, K, overflow);
+  GS_LAUNCHED("clamp_count");
+  return GS_OK;
+}
+
+gs_status sort_reserve(Ctx* ctx, SortScratch& ss, uint32_t n) {
+  const uint32_t nb = nblocks_of(n);
+  const uint32_t hist_n = (uint32_t)kRadix * nb;
+  const uint32_t hb = nblocks_of(hist_n);
+  return ensure_scratch(ctx, ss, hb > nb ? hb : nb, hist_n);
+}
+
+gs_status launch_tile_order(Frame& f, hipStream_t s) {
+  const uint32_t tiles = (uint32_t)f.vt.total_tiles;
+  for (int k = 0; k < 2; ++k) {
+    gs_status st = buf_ensure(f.ctx, f.okey[k], (size_t)tiles * 4);
+    if (st == GS_OK) st = buf_ensure(f.ctx, f.oval[k], (size_t)tiles * 4);
+    if (st != GS_OK) return st;
+  }
+  // keys into okey[1]; the sort reads them and ping-pongs okey[0] <-> okey[1]
+  hipLaunchKernelGGL(k_tile_len_keys, dim3((tiles + 255) / 256), dim3(256), 0, s,
+                     (const uint2*)f.ranges.p, tiles, (uint32_t*)f.okey[1].p);
+  GS_LAUNCHED("tile_len_keys");
+  int in_b = 0;
+  gs_status st = sort_pairs_u32(f.ctx, f.ss, (const uint32_t*)f.okey[1].p, nullptr,
+                                (uint32_t*)f.okey[0].p, (uint32_t*)f.oval[0].p,
+                                (uint32_t*)f.okey[1].p, (uint32_t*)f.oval[1].p, tiles, nullptr,
+                                20, &in_b, s);
+  if (st != GS_OK) return st;
+  f.tile_order = (const uint32_t*)f.oval[in_b].p;
   return GS_OK;
 }
 

@@ -69,8 +69,10 @@ def parse():
     ap.add_argument("--tile", type=int, default=16)
     ap.add_argument("--lds-depth", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-tiles", type=int, default=96, help="tiles in the CPU-baseline sample")
+    ap.add_argument("--cpu-tiles", type=int, default=320, help="tiles in the CPU-baseline sample")
     ap.add_argument("--only", choices=["all", "batched", "plain"], default="all")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=2000)
     return ap.parse_args()
 
 
@@ -87,14 +89,35 @@ def make_targets(scene, cams_d, coarse=128):
     return out
 
 
-def run_steps(P, ctx, params, cams, targets, steps, warmup, tile, depth, torch):
+def run_graph(P, ctx, params, cams, targets, steps, warmup, render, with_adam, torch):
+    """Time `steps` replays of the captured step; returns per-step ms and records."""
+    g = P.StepGraph(ctx, params, cams, targets, with_adam=with_adam, render=render)
+    for _ in range(warmup):
+        g.run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        g.launch()
+    over, rec = g.sync()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    if over:
+        raise RuntimeError("record capacity overflowed during the timed replays")
+    loss = float(g.loss.item())
+    cap, _ = g.info()
+    g.close()
+    return ms, rec, cap, loss
+
+
+def run_steps(P, ctx, params, cams, targets, steps, warmup, tile, depth, torch, flags=0):
     """Time `steps` fwd+bwd steps; returns per-step ms, stage totals and a frame."""
     frame = P.Frame()
     images = [torch.empty((3, c.height, c.width), device="cuda") for c in cams]
     grads = params.zeros_like()
 
     def one():
-        P.render_fwd(ctx, params, cams, images, tile=tile, lds_depth=depth, frame=frame)
+        P.render_fwd(ctx, params, cams, images, tile=tile, lds_depth=depth, flags=flags,
+                     frame=frame)
         loss, dl = P.loss_grad(ctx, images, targets, cams)
         P.render_bwd(ctx, frame, params, dl, grads)
         return loss
@@ -111,6 +134,89 @@ def run_steps(P, ctx, params, cams, targets, steps, warmup, tile, depth, torch):
     stages = ctx.stage_times()
     ctx.set_timing(False)
     return ms, stages, frame, float(loss.item()), images, grads
+
+
+def serve_run(P, ctx, scene_params, requests, arrivals, outs, warm_cams, torch, **server_opts):
+    """Replay the arrival process against a server; returns its statistics."""
+    srv = P.Server(ctx, **server_opts)
+    ids = [srv.add_scene(p) for p in scene_params]
+    # warm-up: a burst over every (scene, size) so every slot has sized its buffers
+    warm = []
+    for _ in range(server_opts.get("n_slots", 1)):
+        for sid in ids:
+            for size, ring in outs.items():
+                warm.append(srv.submit(sid, warm_cams[size], ring[len(warm) % len(ring)][0])[0])
+    for t in warm:
+        srv.wait(t)
+    srv.drain()
+    srv.reset_stats()
+    busy = {size: [None] * len(ring) for size, ring in outs.items()}
+    nxt = {size: 0 for size in outs}
+    t0 = time.perf_counter()
+    for (sid, cams), at in zip(requests, arrivals):
+        ((size, cam),) = cams.items()
+        k = nxt[size] % len(outs[size])
+        nxt[size] += 1
+        if busy[size][k] is not None:          # output buffer still in use
+            srv.wait(busy[size][k])
+        delay = t0 + at - time.perf_counter()
+        if delay > 0:
+            time.sleep(delay)
+        t, _ = srv.submit(ids[sid], cam, outs[size][k][0])
+        busy[size][k] = t
+    srv.drain()
+    st = srv.stats()
+    srv.close()
+    return st
+
+
+def serve_bench(P, ctx, params4m, torch, n_requests=2000, rate=200.0):
+    """Three resident scenes (100k, 1M, 4M Gaussians, SH3); Poisson arrivals; sizes
+    512^2 / 1024^2 / 2048^2; batched server vs serial per-request rendering."""
+    import gsscenes
+    t0 = time.perf_counter()
+    s100k = gsscenes.make_scene("serve")
+    s1m = gsscenes.make_scene("iso1m")
+    scenes = [P.Params.from_numpy(s100k.params), P.Params.from_numpy(s1m.params), params4m]
+    log(f"serve scenes in {time.perf_counter() - t0:.1f}s")
+    arrivals, u_scene, u_size = gsscenes.arrival_times(rate, n_requests)
+    sizes = [512, 1024, 2048]
+    orbit = {s: P.orbit_cameras(64, 2.5, 60.0, s, s) for s in sizes}
+    requests = []
+    for i in range(n_requests):
+        sid = min(int(u_scene[i] * 3), 2)
+        s = sizes[min(int(u_size[i] * 3), 2)]
+        requests.append((sid, {s: orbit[s][(i * 37) % 64]}))
+    outs = {s: [(torch.empty((3, s, s), device="cuda"),) for _ in range(32)] for s in sizes}
+    warm = {s: orbit[s][1] for s in sizes}
+    pix = sum(next(iter(c)) ** 2 for _, c in requests)
+    res = {}
+    for name, opts in (("batched", dict(n_slots=4, max_batch_views=8)),
+                       ("serial", dict(n_slots=1, max_batch_views=1))):
+        st = serve_run(P, ctx, scenes, requests, arrivals, outs, warm, torch, **opts)
+        res[name] = {"p50_ms": round(st["p50_ms"], 3), "p99_ms": round(st["p99_ms"], 3),
+                     "mean_ms": round(st["mean_ms"], 3), "max_ms": round(st["max_ms"], 3),
+                     "mpix_per_s": round(st["mpix_per_s"], 1), "completed": st["completed"],
+                     "batches": st["batches"], "mean_batch_views": round(st["mean_batch_views"], 2),
+                     "deferred": st["deferred"], "peak_scratch_bytes": st["peak_bytes"],
+                     "slots": opts["n_slots"], "max_batch_views": opts["max_batch_views"]}
+        log(f"serve {name}: p50 {st['p50_ms']:.2f} ms, p99 {st['p99_ms']:.2f} ms, "
+            f"{st['mpix_per_s']:.0f} Mpix/s")
+    # saturation: the same requests submitted at once (offered load far above capacity)
+    burst = [0.0] * min(600, n_requests)
+    for name, opts in (("batched_saturated", dict(n_slots=4, max_batch_views=8)),
+                       ("serial_saturated", dict(n_slots=1, max_batch_views=1))):
+        st = serve_run(P, ctx, scenes, requests[:len(burst)], burst, outs, warm, torch, **opts)
+        res[name] = {"mpix_per_s": round(st["mpix_per_s"], 1), "p50_ms": round(st["p50_ms"], 3),
+                     "p99_ms": round(st["p99_ms"], 3),
+                     "mean_batch_views": round(st["mean_batch_views"], 2)}
+        log(f"serve {name}: {st['mpix_per_s']:.0f} Mpix/s")
+    res["workload"] = (f"{n_requests} requests, Poisson {rate:.0f}/s, scenes 100k/1M/4M "
+                       f"Gaussians (SH3) resident, sizes 512^2/1024^2/2048^2 uniform, "
+                       f"{pix / 1e6:.0f} Mpix total")
+    for s in scenes[:2]:
+        del s
+    return res
 
 
 def frame_counts(frame, n, torch):
@@ -260,14 +366,34 @@ def main():
     torch.cuda.synchronize()
 
     res = {}
+    tune = None
     if args.only in ("all", "batched"):
+        t0 = time.perf_counter()
+        best, table = P.autotune(ctx, params, cams, reps=2, use_cache=False, cache=None)
+        tune = {"best": best, "seconds": round(time.perf_counter() - t0, 2),
+                "table": sorted(table, key=lambda r: r["ms"])[:6]}
+        log(f"autotune: best {best} in {tune['seconds']}s")
+        # eager run of the tuned configuration: per-stage HIP-event times
         ms, stages, frame, loss, _, _ = run_steps(P, ctx, params, cams, targets, args.steps,
-                                                  args.warmup, args.tile, args.lds_depth, torch)
+                                                  args.warmup, best["tile"], best["lds_depth"],
+                                                  torch, flags=best["flags"])
         st, pairs, vis = frame_counts(frame, n, torch)
         res["batched"] = dict(ms=ms, stages=stages, K=st["n_records"], pixels=st["n_pixels"],
                               pairs=pairs, visible=vis, views=4, loss=loss)
-        log(f"batched: {ms:.2f} ms/step, K={st['n_records']}, pairs={pairs}")
+        log(f"batched (eager, tuned): {ms:.2f} ms/step, K={st['n_records']}, pairs={pairs}")
         frame.release()
+        # the captured step: fwd+bwd, then fwd+bwd+Adam
+        gms, rec, cap, gloss = run_graph(P, ctx, params, cams, targets, args.steps, args.warmup,
+                                         best, False, torch)
+        res["batched_graph"] = dict(ms=gms, K=rec, capacity=cap, pixels=st["n_pixels"], views=4,
+                                    loss=gloss, visible=vis, pairs=pairs, stages={})
+        log(f"batched (graph): {gms:.2f} ms/step")
+        pa = P.Params(*(t.clone() for t in params.tensors()), params.sh_degree)
+        ams, _, _, _ = run_graph(P, ctx, pa, cams, targets, args.steps, args.warmup, best, True,
+                                 torch)
+        res["batched_graph"]["ms_with_adam"] = ams
+        del pa
+        log(f"batched (graph + Adam): {ams:.2f} ms/step")
     if args.only in ("all", "plain"):
         ms, stages, frame, loss, _, _ = run_steps(P, ctx, params, cams[:1], targets[:1],
                                                   args.steps, args.warmup, args.tile,
@@ -305,38 +431,55 @@ def main():
     probe_gbs = 2 * probe_bytes / (probe_ms * 1e-3) / 1e9
     del src, dst
 
-    head = res.get("batched") or res["plain"]
-    form = "batched" if "batched" in res else "plain"
+    # headline: the captured batched step; roofline from the eager run of the same
+    # (tuned) configuration, whose per-stage HIP-event times are the same kernels
+    head = res.get("batched_graph") or res["plain"]
+    eager = res.get("batched") or res["plain"]
+    form = "batched_graph" if "batched_graph" in res else "plain"
     value = head["pixels"] / (head["ms"] * 1e-3) / 1e6
-    dom, roof = roofline(head["stages"], args.steps, n, head["views"], head["visible"], head["K"],
-                         head["pixels"], head["pairs"])
-    roof["traffic"] = measured_traffic(dom, head["views"]) if args.n is None else None
+    dom, roof = roofline(eager["stages"], args.steps, n, eager["views"], eager["visible"],
+                         eager["K"], eager["pixels"], eager["pairs"])
+    roof["traffic"] = (measured_traffic(dom, eager["views"])
+                       if args.n is None and tune is not None
+                       and (tune["best"]["tile"], tune["best"]["lds_depth"],
+                            tune["best"]["flags"]) == (16, 256, 0) else None)
+    if form == "batched_graph":
+        wl = (f"kingsnake4m: {n} Gaussians on a seeded 1024^3 blob+noise isosurface, SH3; "
+              f"batched form: 4 views (2x2048^2 + 2x1536^2) per step, one hipGraph replay "
+              f"(projection, sort, persistent/grid blend, loss gradient, backward), tuned "
+              f"tile {tune['best']['tile']}, LDS depth {tune['best']['lds_depth']}, "
+              f"flags {tune['best']['flags']}")
+    else:
+        wl = f"kingsnake4m: {n} Gaussians, SH3; plain form: one 2048^2 view per step"
     out = {
         "metric": METRIC, "value": round(value, 3), "unit": "Mpix/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(head["ms"], 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": (f"kingsnake4m: {n} Gaussians on a seeded 1024^3 blob+noise "
-                                f"isosurface, SH3, {form} form"
-                                + (": 4 views (2x2048^2 + 2x1536^2) per step in one call"
-                                   if form == "batched" else ": one 2048^2 view per step")),
-                   "tile": args.tile, "lds_depth": args.lds_depth,
-                   "views_per_step": head["views"], "pixels_per_step": head["pixels"]},
+        "config": {"workload": wl, "views_per_step": head["views"],
+                   "pixels_per_step": head["pixels"], "gaussians": n},
         "gaussians_per_s": round(n * head["views"] / (head["ms"] * 1e-3), 1),
         "roofline": roof,
         "forms": {k: {"ms_per_step": round(r["ms"], 3),
                       "mpix_per_s": round(r["pixels"] / (r["ms"] * 1e-3) / 1e6, 3),
                       "records_K": r["K"], "visible": r["visible"], "pairs": r["pairs"],
                       "loss": round(r["loss"], 6),
+                      **({"ms_with_adam": round(r["ms_with_adam"], 3), "capacity": r["capacity"]}
+                         if "ms_with_adam" in r else {}),
                       "stages_ms_per_step": {s: round(t / args.steps, 4)
                                              for s, (t, c) in r["stages"].items() if c}}
                   for k, r in res.items()},
+        "batched_vs_plain": (round((res["batched_graph"]["pixels"] / res["batched_graph"]["ms"])
+                                   / (res["plain"]["pixels"] / res["plain"]["ms"]), 3)
+                             if "batched_graph" in res and "plain" in res else None),
+        "autotune": tune,
         "adam": {"ms": round(adam_ms, 4), "GBps_algorithmic": round(adam_gbs, 1),
-                 "frac_of_probe": round(adam_gbs / probe_gbs, 4),
-                 "step_ms_with_adam": round(head["ms"] + adam_ms, 3)},
+                 "frac_of_probe": round(adam_gbs / probe_gbs, 4)},
         "hbm_probe": {"GBps": round(probe_gbs, 1), "bytes_per_launch": 2 * probe_bytes,
                       "ms": round(probe_ms, 4), "frac_of_peak": round(probe_gbs / HBM_PEAK_GBS, 4)},
     }
+    if not args.no_serve:
+        out["serve"] = serve_bench(P, ctx, params, torch, n_requests=args.serve_requests)
     if not args.no_cpu_baseline:
         t0 = time.perf_counter()
         out["cpu_baseline"] = cpu_baseline(scene, cams_d[0], targets_np[0], args.cpu_tiles,

@@ -285,6 +285,53 @@ gs_status gs_step_graph_info(gs_graph* graph, int64_t* capacity, int64_t* record
                              gs_frame** frame);
 void gs_step_graph_destroy(gs_graph* graph);
 
+/* ----------------------------------------------------------- render server
+ * Serving of trained scenes (the paper's aim of real-time post hoc and in situ
+ * visualization, Sec. I and V): scenes stay resident on the device and novel
+ * views are rendered on request.  n_slots worker threads (1..8) each own a
+ * HIP stream; a free worker takes the scene of the oldest pending request and
+ * up to max_batch_views of that scene's pending requests (any resolutions)
+ * and renders them as one multi-view forward.  A batch is admitted when its
+ * estimated scratch plus the scratch held by the other slots fits mem_budget
+ * (0 = no limit; an idle device always admits one batch); otherwise it waits
+ * for a running batch to finish.  Latency = submission to completion of the
+ * request's batch.  Stage timing (gs_ctx_set_timing) must be off while a
+ * server runs.  A request's image is the same in any batch. */
+typedef struct {
+  int32_t n_slots;
+  int32_t max_batch_views;
+  size_t mem_budget;
+  gs_render_opts render;
+  int32_t max_queue;         /* pending requests before submit returns GS_ERR_BUSY */
+  int32_t reserved;
+} gs_server_opts;
+
+typedef struct {
+  int64_t submitted, completed, batches, deferred;
+  double mean_batch_views;
+  double p50_ms, p99_ms, mean_ms, max_ms;
+  double mpix_per_s;         /* completed pixels / (last completion - first submission) */
+  int64_t peak_bytes;        /* high-water mark of the admission ledger */
+} gs_serve_stats;
+
+gs_status gs_server_create(gs_ctx* ctx, const gs_server_opts* opts, gs_server** out);
+/* Register a resident scene (device parameters stay caller-owned and must
+ * outlive the server); *scene_id receives its id. */
+gs_status gs_server_add_scene(gs_server* server, gs_params scene, int32_t* scene_id);
+/* Queue a render of `scene` seen from *cam into out_image (device [3][H][W],
+ * caller-owned, untouched until the request completes). */
+gs_status gs_server_submit(gs_server* server, int32_t scene, const gs_camera* cam,
+                           float* out_image, uint64_t* ticket);
+/* Non-blocking completion check (a completed ticket is forgotten after it is
+ * reported), or a blocking wait; latency in ms. */
+gs_status gs_server_poll(gs_server* server, uint64_t ticket, int32_t* done, double* latency_ms);
+gs_status gs_server_wait(gs_server* server, uint64_t ticket, double* latency_ms);
+/* Wait until every submitted request has completed. */
+gs_status gs_server_drain(gs_server* server);
+gs_status gs_server_stats(gs_server* server, gs_serve_stats* out);
+gs_status gs_server_reset_stats(gs_server* server);
+void gs_server_destroy(gs_server* server);
+
 /* -------------------------------------------------------------- autotuner
  * Times forward + backward of the given views for tile sizes {8, 16, 32},
  * LDS depths {32, 64, 128, 256} and the grid or persistent longest-first

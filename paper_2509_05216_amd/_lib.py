@@ -78,6 +78,19 @@ class GsStepDesc(C.Structure):
                 ("capacity_slack", C.c_double)]
 
 
+class GsServerOpts(C.Structure):
+    _fields_ = [("n_slots", C.c_int32), ("max_batch_views", C.c_int32),
+                ("mem_budget", C.c_size_t), ("render", GsRenderOpts), ("max_queue", C.c_int32),
+                ("reserved", C.c_int32)]
+
+
+class GsServeStats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("batches", C.c_int64),
+                ("deferred", C.c_int64), ("mean_batch_views", C.c_double),
+                ("p50_ms", C.c_double), ("p99_ms", C.c_double), ("mean_ms", C.c_double),
+                ("max_ms", C.c_double), ("mpix_per_s", C.c_double), ("peak_bytes", C.c_int64)]
+
+
 class GsTuneEntry(C.Structure):
     _fields_ = [("tile", C.c_int32), ("lds_depth", C.c_int32), ("flags", C.c_int32),
                 ("ms", C.c_float)]
@@ -115,6 +128,16 @@ SIGNATURES = [
     ("gs_step_graph_info", C.c_int, [_P, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
                                      C.POINTER(_P)]),
     ("gs_step_graph_destroy", None, [_P]),
+    ("gs_server_create", C.c_int, [_P, C.POINTER(GsServerOpts), C.POINTER(_P)]),
+    ("gs_server_add_scene", C.c_int, [_P, GsParams, C.POINTER(C.c_int32)]),
+    ("gs_server_submit", C.c_int, [_P, C.c_int32, C.POINTER(GsCamera), _P,
+                                   C.POINTER(C.c_uint64)]),
+    ("gs_server_poll", C.c_int, [_P, C.c_uint64, C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
+    ("gs_server_wait", C.c_int, [_P, C.c_uint64, C.POINTER(C.c_double)]),
+    ("gs_server_drain", C.c_int, [_P]),
+    ("gs_server_stats", C.c_int, [_P, C.POINTER(GsServeStats)]),
+    ("gs_server_reset_stats", C.c_int, [_P]),
+    ("gs_server_destroy", None, [_P]),
     ("gs_autotune", C.c_int, [_P, GsParams, C.POINTER(GsCamera), C.c_int32, C.c_int32,
                               C.POINTER(GsRenderOpts), C.POINTER(GsTuneEntry), C.c_int32,
                               C.POINTER(C.c_int32), _P]),

@@ -32,15 +32,22 @@ gs_status buf_ensure(Ctx* ctx, DevBuf& b, size_t bytes) {
   }
   size_t want = bytes + bytes / 8;
   want = (want + 4095) & ~(size_t)4095;
-  const size_t after = ctx->in_use - b.cap + want;
-  if (ctx->budget != 0 && after > ctx->budget) {
-    set_error("device scratch budget exceeded: need %zu bytes, budget %zu", after, ctx->budget);
-    return GS_ERR_NOMEM;
+  {
+    std::lock_guard<std::mutex> lk(ctx->mem_mutex);
+    const size_t after = ctx->in_use - b.cap + want;
+    if (ctx->budget != 0 && after > ctx->budget) {
+      set_error("device scratch budget exceeded: need %zu bytes, budget %zu", after,
+                ctx->budget);
+      return GS_ERR_NOMEM;
+    }
   }
   if (b.p != nullptr) {
     GS_HIP(hipDeviceSynchronize());  // queued work may still use the old buffer
     GS_HIP(hipFree(b.p));
-    ctx->in_use -= b.cap;
+    {
+      std::lock_guard<std::mutex> lk(ctx->mem_mutex);
+      ctx->in_use -= b.cap;
+    }
     b.p = nullptr;
     b.cap = 0;
   }
@@ -51,6 +58,7 @@ gs_status buf_ensure(Ctx* ctx, DevBuf& b, size_t bytes) {
     return GS_ERR_NOMEM;
   }
   b.cap = want;
+  std::lock_guard<std::mutex> lk(ctx->mem_mutex);
   ctx->in_use += want;
   if (ctx->in_use > ctx->peak) ctx->peak = ctx->in_use;
   return GS_OK;
@@ -59,6 +67,7 @@ gs_status buf_ensure(Ctx* ctx, DevBuf& b, size_t bytes) {
 void buf_free(Ctx* ctx, DevBuf& b) {
   if (b.p != nullptr) {
     (void)hipFree(b.p);
+    std::lock_guard<std::mutex> lk(ctx->mem_mutex);
     ctx->in_use -= b.cap;
   }
   b.p = nullptr;

@@ -20,6 +20,7 @@
 
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <string>
 
 #include "isogs.h"
@@ -135,6 +136,7 @@ struct Ctx {
   size_t budget = 0;
   size_t in_use = 0;
   size_t peak = 0;
+  std::mutex mem_mutex;  // guards in_use / peak (render server workers share a context)
   int cu_count = 0;
   hipDeviceProp_t prop;
   void* loss_scratch = nullptr;  // loss.hip workspace (g maps, block partials)

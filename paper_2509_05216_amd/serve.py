@@ -36,8 +36,9 @@ class Server:
     def submit(self, scene, cam, out=None):
         """Queue a render; returns (ticket, output tensor)."""
         if out is None:
-            out = torch.empty((3, cam.height, cam.width), dtype=torch.float32,
-                              device=self._scenes[scene].means.device)
+            known = 0 <= scene < len(self._scenes)
+            dev = self._scenes[scene].means.device if known else torch.device("cuda")
+            out = torch.empty((3, cam.height, cam.width), dtype=torch.float32, device=dev)
         t = C.c_uint64()
         L.check(L.lib().gs_server_submit(self.handle, scene, C.byref(cam),
                                          C.c_void_p(out.data_ptr()), C.byref(t)))

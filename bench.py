@@ -35,24 +35,23 @@ FP32_PEAK_TFLOPS = 157.3
 FLOP_PAIR_FWD = 23
 FLOP_PAIR_BWD = 68
 # HBM bytes per launch of a kernel, from calibrated rocprofv3 FETCH_SIZE / WRITE_SIZE runs
-# (profiles/hbm_traffic_kingsnake4m.md), valid only while the kernel source is unchanged:
-# the figure is dropped (traffic = null) when the source hash no longer matches.
-MEASURED_TRAFFIC = {
-    "blend_bwd": {"source": "paper_2509_05216_amd/csrc/blend.hip",
-                  "sha256": "1953ad7eb534dcf81ae396938eaec72fad9b5229af48b87b292def31cf2c98aa",
-                  "read_bytes": 2887.4e6, "write_bytes": 3893.5e6, "views": 4},
-}
+# (profiles/hbm_traffic_kingsnake4m.md), one entry per measured launch configuration and
+# valid only while the kernel source is unchanged: when the source hash no longer matches,
+# or the timed configuration was not measured, the figure is null.
+MEASURED_TRAFFIC = []
 
 
-def measured_traffic(kernel, views):
+def measured_traffic(kernel, views, render):
     import hashlib
-    m = MEASURED_TRAFFIC.get(kernel)
-    if m is None or m["views"] != views:
-        return None
-    with open(os.path.join(ROOT, m["source"]), "rb") as fh:
-        if hashlib.sha256(fh.read()).hexdigest() != m["sha256"]:
-            return None
-    return round(m["read_bytes"] + m["write_bytes"])
+    for m in MEASURED_TRAFFIC:
+        if (m["kernel"], m["views"], m["tile"], m["lds_depth"], m["flags"]) != (
+                kernel, views, render["tile"], render["lds_depth"], render["flags"]):
+            continue
+        with open(os.path.join(ROOT, m["source"]), "rb") as fh:
+            if hashlib.sha256(fh.read()).hexdigest() != m["sha256"]:
+                return None
+        return round(m["read_bytes"] + m["write_bytes"])
+    return None
 
 
 def log(msg):
@@ -73,6 +72,10 @@ def parse():
     ap.add_argument("--only", choices=["all", "batched", "plain"], default="all")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--no-graph", action="store_true",
+                    help="skip the graph-captured forms (e.g. for counter collection)")
+    ap.add_argument("--config", default=None,
+                    help="TILE,LDS_DEPTH,FLAGS for the batched form instead of autotuning")
     return ap.parse_args()
 
 
@@ -369,10 +372,15 @@ def main():
     tune = None
     if args.only in ("all", "batched"):
         t0 = time.perf_counter()
-        best, table = P.autotune(ctx, params, cams, reps=2, use_cache=False, cache=None)
-        tune = {"best": best, "seconds": round(time.perf_counter() - t0, 2),
-                "table": sorted(table, key=lambda r: r["ms"])[:6]}
-        log(f"autotune: best {best} in {tune['seconds']}s")
+        if args.config:
+            tl, dp, fl = (int(x) for x in args.config.split(","))
+            best = {"tile": tl, "lds_depth": dp, "flags": fl}
+            tune = {"best": best, "fixed": True}
+        else:
+            best, table = P.autotune(ctx, params, cams, reps=5, use_cache=False, cache=None)
+            tune = {"best": best, "seconds": round(time.perf_counter() - t0, 2),
+                    "table": sorted(table, key=lambda r: r["ms"])[:6]}
+        log(f"batched options: {best}")
         # eager run of the tuned configuration: per-stage HIP-event times
         ms, stages, frame, loss, _, _ = run_steps(P, ctx, params, cams, targets, args.steps,
                                                   args.warmup, best["tile"], best["lds_depth"],
@@ -382,6 +390,7 @@ def main():
                               pairs=pairs, visible=vis, views=4, loss=loss)
         log(f"batched (eager, tuned): {ms:.2f} ms/step, K={st['n_records']}, pairs={pairs}")
         frame.release()
+    if args.only in ("all", "batched") and not args.no_graph:
         # the captured step: fwd+bwd, then fwd+bwd+Adam
         gms, rec, cap, gloss = run_graph(P, ctx, params, cams, targets, args.steps, args.warmup,
                                          best, False, torch)
@@ -439,10 +448,8 @@ def main():
     value = head["pixels"] / (head["ms"] * 1e-3) / 1e6
     dom, roof = roofline(eager["stages"], args.steps, n, eager["views"], eager["visible"],
                          eager["K"], eager["pixels"], eager["pairs"])
-    roof["traffic"] = (measured_traffic(dom, eager["views"])
-                       if args.n is None and tune is not None
-                       and (tune["best"]["tile"], tune["best"]["lds_depth"],
-                            tune["best"]["flags"]) == (16, 256, 0) else None)
+    roof["traffic"] = (measured_traffic(dom, eager["views"], tune["best"])
+                       if args.n is None and args.grid is None and tune is not None else None)
     if form == "batched_graph":
         wl = (f"kingsnake4m: {n} Gaussians on a seeded 1024^3 blob+noise isosurface, SH3; "
               f"batched form: 4 views (2x2048^2 + 2x1536^2) per step, one hipGraph replay "

@@ -15,16 +15,20 @@
 // The forward stops a batch loop once every pixel of the tile has terminated
 // (block-wide vote).  The backward walks the list from the tile's last
 // contributor down to its first, recomputing each pixel's transmittance as
-// T / (1 - alpha) from the final value, so no per-pixel list is stored.
-// Per-pair gradients (9 floats) are reduce-scattered across the wave (two
-// gfx950 permlane swaps, then DPP steps inside 16-lane rows: about 28 VALU
+// T * rcp(1 - alpha) from the final value (1 - alpha >= 0.01, so the 1-ulp
+// hardware reciprocal is ample), so no per-pixel list is stored.  Per-pair
+// gradients (9 floats) are reduce-scattered across the wave (two gfx950
+// permlane swaps, then DPP steps inside 16-lane rows: about 28 VALU
 // instructions for all nine sums), added across the workgroup's waves with
 // LDS float atomics and to the per-Gaussian accumulators with one global
 // atomic per component per (tile, Gaussian).
 //
-// Both kernels evaluate a pair with the same inline code; the library is
-// compiled with -ffp-contract=off, so the backward reproduces the forward's
-// skip/stop decisions exactly.
+// Both walks are branch-free per pair (lanes that skip a pair select zeros),
+// keep two slots' LDS operands in flight, and take each slot index from a
+// 64-entry VGPR copy of the wave's list through readlane.  Both kernels
+// evaluate the skip/stop decisions with the same inline, uncontracted code
+// (the library is compiled with -ffp-contract=off), so the backward
+// reproduces the forward's decisions exactly.
 #include "internal.h"
 
 namespace isogs {
@@ -143,6 +147,41 @@ struct Layout {
   }
 };
 
+// A wave's compacted slot list, read 64 entries at a time into one VGPR; the
+// entry at a wave-uniform position comes back as a scalar through readlane, so
+// the walk needs no LDS round trip per slot for its index.
+template <int NT, int DEPTH>
+struct WaveList {
+  const uint16_t* row;
+  int lv = 0, chunk = -1;
+  __device__ WaveList(const Stage<NT, DEPTH>& st, int wave) : row(st.list[wave]) {}
+  __device__ int at(int kk) {
+    const int c = kk >> 6;
+    if (c != chunk) {
+      chunk = c;
+      lv = row[min(c * 64 + (int)__lane_id(), DEPTH - 1)];
+    }
+    return __builtin_amdgcn_readlane(lv, kk & 63);
+  }
+};
+
+// Operands of one staged splat, read from LDS (same address in every lane).
+struct Slot {
+  int j;
+  float4 q0, q1;
+  float3 q2;
+};
+
+template <int NT, int DEPTH>
+__device__ inline Slot load_slot(const Stage<NT, DEPTH>& st, int j) {
+  Slot s;
+  s.j = j;
+  s.q0 = st.s0[j];
+  s.q1 = st.s1[j];
+  s.q2 = make_float3(st.s2[j].x, st.s2[j].y, st.s2[j].z);
+  return s;
+}
+
 // Forward of one tile (global tile id gt) by the whole workgroup.
 template <int TILE, int DEPTH>
 __device__ inline void fwd_tile(Stage<TILE * TILE, DEPTH>& st, const ViewTable& vt, int gt,
@@ -167,30 +206,37 @@ __device__ inline void fwd_tile(Stage<TILE * TILE, DEPTH>& st, const ViewTable& 
     if (__syncthreads_count(done) == NT) break;
     const int cnt = (int)min((uint32_t)DEPTH, rg.y - base);
     stage_batch<TILE, DEPTH>(st, tval, splat, base, cnt, tile_x * TILE, tile_y * TILE);
-    const int nw = (int)st.count[wave];
-    if (!done) {
-      for (int k = 0; k < nw; ++k) {
-        const int j = st.list[wave][k];
-        const float4 q0 = st.s0[j], q1 = st.s1[j];
-        float dx, dy, power;
-        pair_eval(q0.x, q0.y, q0.z, __float_as_int(q1.x), __float_as_int(q1.y), q1.z, q1.w, px,
-                  py, dx, dy, power);
-        if (power > 0.f) continue;
-        const float alpha = fminf(kAlphaMax, q0.w * __expf(power));
-        if (alpha < kAlphaMin) continue;
-        const float Tn = T * (1.f - alpha);
-        if (Tn < kTMin) {
-          done = true;
-          break;
-        }
-        const float4 q2 = st.s2[j];
-        const float w = alpha * T;
-        cr += q2.x * w;
-        cg += q2.y * w;
-        cb += q2.z * w;
-        T = Tn;
-        last = base + (uint32_t)j - rg.x + 1u;
-      }
+    const int nw = __builtin_amdgcn_readfirstlane((int)st.count[wave]);
+    if (nw == 0 || !__any(!done)) continue;
+    WaveList<NT, DEPTH> wl(st, wave);
+    // Branch-free front-to-back step; a lane that has stopped keeps its state.
+    auto step = [&](const Slot& s) {
+      const float4 q0 = s.q0, q1 = s.q1;
+      float dx, dy, power;
+      pair_eval(q0.x, q0.y, q0.z, __float_as_int(q1.x), __float_as_int(q1.y), q1.z, q1.w, px, py,
+                dx, dy, power);
+      const float alpha = fminf(kAlphaMax, q0.w * __expf(power));
+      bool use = !done && !(power > 0.f) && !(alpha < kAlphaMin);
+      const float Tn = T * (1.f - alpha);
+      const bool stop = use && Tn < kTMin;
+      done = done || stop;
+      use = use && !stop;
+      const float w = alpha * T;
+      cr = use ? cr + s.q2.x * w : cr;
+      cg = use ? cg + s.q2.y * w : cg;
+      cb = use ? cb + s.q2.z * w : cb;
+      T = use ? Tn : T;
+      last = use ? base + (uint32_t)s.j - rg.x + 1u : last;
+    };
+    // two slots in flight: the LDS reads of one overlap the arithmetic of the other
+    Slot a = load_slot(st, wl.at(0));
+    for (int k = 0; k < nw; k += 2) {
+      const bool two = k + 1 < nw;
+      const Slot b = load_slot(st, wl.at(two ? k + 1 : k));
+      step(a);
+      a = load_slot(st, wl.at(min(k + 2, nw - 1)));
+      if (two) step(b);
+      if (!__any(!done)) break;
     }
   }
   if (inside) {
@@ -350,7 +396,7 @@ __device__ inline void bwd_tile(BwdSmem<TILE, DEPTH>& sm, const ViewTable& vt, i
   uint32_t m = nc;
 #pragma unroll
   for (int d = 32; d >= 1; d >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, d, 64));
-  const int wave_n = (int)m;
+  const int wave_n = __builtin_amdgcn_readfirstlane((int)m);
   if (lane == 0) smax[wave] = m;
   __syncthreads();
   uint32_t maxn = 0;
@@ -364,50 +410,64 @@ __device__ inline void bwd_tile(BwdSmem<TILE, DEPTH>& sm, const ViewTable& vt, i
     stage_batch<TILE, DEPTH>(st, tval, splat, rg.x + (uint32_t)lo, cnt, tile_x * TILE,
                              tile_y * TILE);
     // walk this wave's overlapping slots from the back, below its last contributor
-    int k = (int)st.count[wave] - 1;
-    while (k >= 0 && lo + (int)st.list[wave][k] >= wave_n) --k;
-    for (; k >= 0; --k) {
-      const int j = st.list[wave][k];
-      const int pos = lo + j;  // position in the tile list
+    WaveList<NT, DEPTH> wl(st, wave);
+    int k = __builtin_amdgcn_readfirstlane((int)st.count[wave]) - 1;
+    while (k >= 0 && lo + wl.at(k) >= wave_n) --k;
+    // One pair (this lane's pixel, slot s) of the reverse walk.
+    auto pair = [&](const Slot& s) {
+      const float4 q0 = s.q0, q1 = s.q1;
+      const float3 q2 = s.q2;
+      // the skip decisions are the forward's, from the same uncontracted expressions
+      float dx, dy, power;
+      pair_eval(q0.x, q0.y, q0.z, __float_as_int(q1.x), __float_as_int(q1.y), q1.z, q1.w, px, py,
+                dx, dy, power);
+      const float G = __expf(power);
+      const float a_raw = q0.w * G;
+      const float alpha = fminf(kAlphaMax, a_raw);
+      const bool contrib =
+          inside && (uint32_t)(lo + s.j) < nc && !(power > 0.f) && !(alpha < kAlphaMin);
+      if (!__any(contrib)) return;
+      // Gradient arithmetic, branch-free: a lane that does not contribute selects
+      // zeros, so its nine values are exactly 0 and its state is unchanged.
+      // 1 - alpha >= 0.01, so the hardware reciprocal (1 ulp) is safe here.
+      const float inv = __builtin_amdgcn_rcpf(1.f - alpha);
+      const float Tb = T * inv;  // transmittance before this record
+      T = contrib ? Tb : T;
+      const float w = contrib ? alpha * Tb : 0.f;
+      float dalpha = dr * fmaf(q2.x, Tb, -Sr * inv);
+      dalpha = fmaf(dg, fmaf(q2.y, Tb, -Sg * inv), dalpha);
+      dalpha = fmaf(db, fmaf(q2.z, Tb, -Sb * inv), dalpha);
+      Sr = fmaf(q2.x, w, Sr);
+      Sg = fmaf(q2.y, w, Sg);
+      Sb = fmaf(q2.z, w, Sb);
+      // alpha clamped at its maximum has zero derivative
+      const bool open = contrib && a_raw <= kAlphaMax;
+      dalpha = open ? dalpha : 0.f;
+      const float dpow = dalpha * alpha;
+      const float hp = -0.5f * dpow;
       float g[9];
-#pragma unroll
-      for (int q = 0; q < 9; ++q) g[q] = 0.f;
-      bool contrib = inside && (uint32_t)pos < nc;
-      if (contrib) {
-        const float4 q0 = st.s0[j], q1 = st.s1[j];
-        float dx, dy, power;
-        pair_eval(q0.x, q0.y, q0.z, __float_as_int(q1.x), __float_as_int(q1.y), q1.z, q1.w, px,
-                  py, dx, dy, power);
-        const float G = __expf(power);
-        const float a_raw = q0.w * G;
-        const float alpha = fminf(kAlphaMax, a_raw);
-        if (power > 0.f || alpha < kAlphaMin) {
-          contrib = false;
-        } else {
-          const float4 q2 = st.s2[j];
-          const float oma = 1.f - alpha;
-          T = T / oma;  // transmittance before this record
-          const float w = alpha * T;
-          g[6] = w * dr;
-          g[7] = w * dg;
-          g[8] = w * db;
-          const float dalpha = dr * (q2.x * T - Sr / oma) + dg * (q2.y * T - Sg / oma) +
-                               db * (q2.z * T - Sb / oma);
-          Sr += q2.x * w;
-          Sg += q2.y * w;
-          Sb += q2.z * w;
-          if (a_raw <= kAlphaMax) {
-            const float dpow = dalpha * alpha;
-            g[5] = dalpha * G;
-            g[2] = -0.5f * dpow * dx * dx;
-            g[3] = -dpow * dx * dy;
-            g[4] = -0.5f * dpow * dy * dy;
-            g[0] = dpow * (q0.x * dx + q0.y * dy);
-            g[1] = dpow * (q0.y * dx + q0.z * dy);
-          }
-        }
+      g[0] = dpow * fmaf(q0.x, dx, q0.y * dy);
+      g[1] = dpow * fmaf(q0.y, dx, q0.z * dy);
+      g[2] = hp * dx * dx;
+      g[3] = -dpow * dx * dy;
+      g[4] = hp * dy * dy;
+      g[5] = open ? dalpha * G : 0.f;
+      g[6] = w * dr;
+      g[7] = w * dg;
+      g[8] = w * db;
+      wave_reduce_add(g, &part[s.j * 9]);
+    };
+    // two slots in flight: the LDS reads of one overlap the arithmetic of the other
+    if (k >= 0) {
+      Slot a = load_slot(st, wl.at(k));
+      while (k >= 1) {
+        const Slot b = load_slot(st, wl.at(k - 1));
+        pair(a);
+        a = load_slot(st, wl.at(max(k - 2, 0)));
+        pair(b);
+        k -= 2;
       }
-      if (__any(contrib)) wave_reduce_add(g, &part[j * 9]);
+      if (k == 0) pair(a);
     }
     __syncthreads();
     for (int t = threadIdx.x; t < cnt * 9; t += NT) {

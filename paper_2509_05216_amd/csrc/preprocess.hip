@@ -132,21 +132,23 @@ struct Proj {
   double xz, yz, u, v, limx, limy;
   double J00, J02, J11, J12;
   double T0[3], T1[3];
+  double S0[3], S1[3];  // Sigma3 T0, Sigma3 T1
   double a, b, c, det;
   double mx, my;
   int radius;
   int x0, y0, x1, y1;  // tile rectangle (inclusive); empty if !touched
-  bool touched;
+  bool visible, touched;
 };
 
-__device__ inline void project_view(const Body& b, const CamDev& c, int tile, Proj& p) {
+// Camera-space mean, Jacobian and 2-D covariance (with the low-pass) of one view.
+__device__ inline void view_cov(const double* mu, const double* Sig, const CamDev& c, Proj& p) {
   const float* R = c.R;
   for (int r = 0; r < 3; ++r)
-    p.t[r] = (double)R[r * 3 + 0] * b.mu[0] + (double)R[r * 3 + 1] * b.mu[1] +
-             (double)R[r * 3 + 2] * b.mu[2] + (double)c.t[r];
+    p.t[r] = (double)R[r * 3 + 0] * mu[0] + (double)R[r * 3 + 1] * mu[1] +
+             (double)R[r * 3 + 2] * mu[2] + (double)c.t[r];
   p.touched = false;
-  const bool visible = p.t[2] > (double)c.znear;
-  const double tz = visible ? p.t[2] : 1.0;
+  p.visible = p.t[2] > (double)c.znear;
+  const double tz = p.visible ? p.t[2] : 1.0;
   const double fx = c.fx, fy = c.fy;
   p.limx = kGuard * (0.5 * (double)c.W / fx);
   p.limy = kGuard * (0.5 * (double)c.H / fy);
@@ -162,10 +164,11 @@ __device__ inline void project_view(const Body& b, const CamDev& c, int tile, Pr
     p.T0[j] = p.J00 * (double)R[0 * 3 + j] + p.J02 * (double)R[2 * 3 + j];
     p.T1[j] = p.J11 * (double)R[1 * 3 + j] + p.J12 * (double)R[2 * 3 + j];
   }
-  double S0[3], S1[3];
+  double* S0 = p.S0;
+  double* S1 = p.S1;
   for (int r = 0; r < 3; ++r) {
-    S0[r] = b.Sig[r * 3 + 0] * p.T0[0] + b.Sig[r * 3 + 1] * p.T0[1] + b.Sig[r * 3 + 2] * p.T0[2];
-    S1[r] = b.Sig[r * 3 + 0] * p.T1[0] + b.Sig[r * 3 + 1] * p.T1[1] + b.Sig[r * 3 + 2] * p.T1[2];
+    S0[r] = Sig[r * 3 + 0] * p.T0[0] + Sig[r * 3 + 1] * p.T0[1] + Sig[r * 3 + 2] * p.T0[2];
+    S1[r] = Sig[r * 3 + 0] * p.T1[0] + Sig[r * 3 + 1] * p.T1[1] + Sig[r * 3 + 2] * p.T1[2];
   }
   p.a = p.T0[0] * S0[0] + p.T0[1] * S0[1] + p.T0[2] * S0[2] + kLowpass;
   p.b = p.T0[0] * S1[0] + p.T0[1] * S1[1] + p.T0[2] * S1[2];
@@ -173,8 +176,13 @@ __device__ inline void project_view(const Body& b, const CamDev& c, int tile, Pr
   p.det = p.a * p.c - p.b * p.b;
   p.mx = fx * p.xz + (double)c.cx;
   p.my = fy * p.yz + (double)c.cy;
+}
+
+// view_cov plus the radius and the tile rectangle (the binning decisions).
+__device__ inline void project_view(const Body& b, const CamDev& c, int tile, Proj& p) {
+  view_cov(b.mu, b.Sig, c, p);
   p.radius = 0;
-  if (!visible || !(p.det > 0)) return;
+  if (!p.visible || !(p.det > 0)) return;
   const double half = 0.5 * (p.a - p.c);
   const double lmax = 0.5 * (p.a + p.c) + sqrt(half * half + p.b * p.b);
   const double r = ceil(3.0 * sqrt(fmax(lmax, 0.0)));
@@ -260,6 +268,15 @@ __global__ __launch_bounds__(256) void k_preprocess_fwd(ParamsDev prm, ViewTable
 }
 
 // Chain rule from the screen-space accumulators (9 per view) to the parameters.
+//
+// Three phases keep few values live at a time:
+//  1. geometry, float64, per view: conic and mean2D gradients -> dL/dt (camera
+//     space) -> dL/dmean, and dL/dSigma3 summed over the views (dL/dSigma3 is
+//     all that the scale and rotation gradients need, so their chain runs once);
+//  2. SH colour, float32, per view: dL/d(SH coefficients) and the gradient of
+//     the view direction with respect to the mean; the accumulators are
+//     cleared for the next pass here;
+//  3. scale and rotation from the summed dL/dSigma3.
 template <int DEG>
 __global__ __launch_bounds__(256) void k_preprocess_bwd(ParamsDev prm, ViewTable vt,
                                                         float* __restrict__ acc,
@@ -271,102 +288,54 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(ParamsDev prm, ViewTable
   if (i >= n) return;
   constexpr int deg = DEG;
   constexpr int nb = (DEG + 1) * (DEG + 1);
-  Body b;
-  bool loaded = false;
-  double g_mu[3] = {0, 0, 0}, g_ls[3] = {0, 0, 0}, g_q[4] = {0, 0, 0, 0}, g_logit = 0;
-  float g_sh[nb * 3];
-#pragma unroll
-  for (int j = 0; j < nb * 3; ++j) g_sh[j] = 0.f;
-  bool any = false;
+
+  // ---- 1. geometry
+  double mu[3], Sig[9];
+  bool loaded = false, any = false;
+  double g_mu[3] = {0, 0, 0}, g_op = 0;
+  double Gs[6] = {0, 0, 0, 0, 0, 0};  // dL/dSigma3 (symmetrised): 00 01 02 11 12 22
   for (int v = 0; v < vt.n; ++v) {
     const size_t o = (size_t)v * n + i;
     const uint2 rc = rect[o];
     if ((rc.y & 0xffffu) < (rc.x & 0xffffu)) continue;  // untouched in this view
-    float4* a = reinterpret_cast<float4*>(acc + o * kAccStride);
-    const float4 a0 = a[0], a1 = a[1], a2 = a[2];
-    const float gs[9] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w, a2.x};
-    bool nz = false;
-#pragma unroll
-    for (int k = 0; k < 9; ++k) nz |= gs[k] != 0.f;
-    if (!nz) continue;
-    // leave the accumulator cleared for the next backward pass
-    const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
-    a[0] = zero4;
-    a[1] = zero4;
-    a[2] = zero4;
-    any = true;
+    const float4* a = reinterpret_cast<const float4*>(acc + o * kAccStride);
+    const float4 a0 = a[0], a1 = a[1];
+    if (a0.x == 0.f && a0.y == 0.f && a0.z == 0.f && a0.w == 0.f && a1.x == 0.f && a1.y == 0.f)
+      continue;
     if (!loaded) {
+      Body b;
       load_body(prm, i, b);
+      for (int k = 0; k < 3; ++k) mu[k] = b.mu[k];
+      for (int k = 0; k < 9; ++k) Sig[k] = b.Sig[k];
       loaded = true;
     }
     const CamDev& c = vt.v[v];
     Proj p;
-    project_view(b, c, vt.tile, p);
-    const double gmx = gs[0], gmy = gs[1], gA = gs[2], gB = gs[3], gC = gs[4];
-    const double gop = gs[5];
-    // opacity
-    {
-      const double o = 1.0 / (1.0 + exp(-(double)prm.logits[i]));
-      g_logit += gop * o * (1.0 - o);
-    }
-    // SH colour
-    {
-      const uint32_t mask = clampm[o];
-      const float grgb[3] = {(mask & 1u) ? 0.f : gs[6], (mask & 2u) ? 0.f : gs[7],
-                             (mask & 4u) ? 0.f : gs[8]};
-      float dx = (float)b.mu[0] - c.campos[0];
-      float dy = (float)b.mu[1] - c.campos[1];
-      float dz = (float)b.mu[2] - c.campos[2];
-      const float len = sqrtf(dx * dx + dy * dy + dz * dz);
-      const float inv = 1.0f / len;
-      dx *= inv;
-      dy *= inv;
-      dz *= inv;
-      float Y[16];
-      sh_basis(dx, dy, dz, deg, Y);
-      float w[16];
-#pragma unroll
-      for (int j = 0; j < nb; ++j) {
-        float s = 0.f;
-#pragma unroll
-        for (int ch = 0; ch < 3; ++ch) {
-          g_sh[j * 3 + ch] += Y[j] * grgb[ch];
-          s += prm.sh[(size_t)(j * 3 + ch) * n + i] * grgb[ch];
-        }
-        w[j] = s;
-      }
-      float gx = 0.f, gy = 0.f, gz = 0.f;
-      sh_basis_grad_dot(dx, dy, dz, deg, w, gx, gy, gz);
-      const float dot = gx * dx + gy * dy + gz * dz;
-      g_mu[0] += (double)((gx - dx * dot) * inv);
-      g_mu[1] += (double)((gy - dy * dot) * inv);
-      g_mu[2] += (double)((gz - dz * dot) * inv);
-    }
+    view_cov(mu, Sig, c, p);
+    const double gmx = a0.x, gmy = a0.y, gA = a0.z, gB = a0.w, gC = a1.x;
+    g_op += a1.y;
     // conic (A, B, C) = (c, -b, a) / det
     const double D = p.det;
     const double gD = -(gA * p.c - gB * p.b + gC * p.a) / (D * D);
     const double ga = gC / D + gD * p.c;
     const double gb = -gB / D - 2.0 * gD * p.b;
     const double gc = gA / D + gD * p.a;
-    // Sigma2 = T Sigma3 T^T
-    double S0[3], S1[3];
-    for (int r = 0; r < 3; ++r) {
-      S0[r] = b.Sig[r * 3 + 0] * p.T0[0] + b.Sig[r * 3 + 1] * p.T0[1] + b.Sig[r * 3 + 2] * p.T0[2];
-      S1[r] = b.Sig[r * 3 + 0] * p.T1[0] + b.Sig[r * 3 + 1] * p.T1[1] + b.Sig[r * 3 + 2] * p.T1[2];
-    }
+    // Sigma2 = T Sigma3 T^T: dL/dT rows, and G + G^T with
+    // G = ga T0 T0^T + gb T0 T1^T + gc T1 T1^T
     double gT0[3], gT1[3];
     for (int r = 0; r < 3; ++r) {
-      gT0[r] = 2.0 * ga * S0[r] + gb * S1[r];
-      gT1[r] = gb * S0[r] + 2.0 * gc * S1[r];
+      gT0[r] = 2.0 * ga * p.S0[r] + gb * p.S1[r];
+      gT1[r] = gb * p.S0[r] + 2.0 * gc * p.S1[r];
     }
-    // dL/dSigma3 (symmetrised): Gs = G + G^T, G = ga T0 T0^T + gb T0 T1^T + gc T1 T1^T
-    double Gs[9];
-    for (int r = 0; r < 3; ++r)
-      for (int q = 0; q < 3; ++q) {
-        const double g1 = ga * p.T0[r] * p.T0[q] + gb * p.T0[r] * p.T1[q] + gc * p.T1[r] * p.T1[q];
-        const double g2 = ga * p.T0[q] * p.T0[r] + gb * p.T0[q] * p.T1[r] + gc * p.T1[q] * p.T1[r];
-        Gs[r * 3 + q] = g1 + g2;
-      }
+    {
+      int k = 0;
+      for (int r = 0; r < 3; ++r)
+        for (int q = r; q < 3; ++q, ++k) {
+          const double g1 = ga * p.T0[r] * p.T0[q] + gb * p.T0[r] * p.T1[q] + gc * p.T1[r] * p.T1[q];
+          const double g2 = ga * p.T0[q] * p.T0[r] + gb * p.T0[q] * p.T1[r] + gc * p.T1[q] * p.T1[r];
+          Gs[k] += g1 + g2;
+        }
+    }
     // T = J R  ->  dJ = dT R^T (only the four non-zero Jacobian entries matter)
     const float* R = c.R;
     double gJ00 = 0, gJ02 = 0, gJ11 = 0, gJ12 = 0;
@@ -398,6 +367,76 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(ParamsDev prm, ViewTable
     for (int k = 0; k < 3; ++k)
       g_mu[k] += (double)R[0 * 3 + k] * gt[0] + (double)R[1 * 3 + k] * gt[1] +
                  (double)R[2 * 3 + k] * gt[2];
+  }
+
+  // ---- 2. SH colour (float32); clears the accumulators
+  float g_sh[nb * 3];
+#pragma unroll
+  for (int j = 0; j < nb * 3; ++j) g_sh[j] = 0.f;
+  float gmf[3] = {0.f, 0.f, 0.f};
+  float mf[3] = {0.f, 0.f, 0.f};
+  bool mf_loaded = false;
+  for (int v = 0; v < vt.n; ++v) {
+    const size_t o = (size_t)v * n + i;
+    const uint2 rc = rect[o];
+    if ((rc.y & 0xffffu) < (rc.x & 0xffffu)) continue;
+    float4* a = reinterpret_cast<float4*>(acc + o * kAccStride);
+    const float4 a0 = a[0], a1 = a[1], a2 = a[2];
+    const bool geo = a0.x != 0.f || a0.y != 0.f || a0.z != 0.f || a0.w != 0.f || a1.x != 0.f ||
+                     a1.y != 0.f;
+    const bool col = a1.z != 0.f || a1.w != 0.f || a2.x != 0.f;
+    if (!geo && !col) continue;
+    // leave the accumulator cleared for the next backward pass
+    const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
+    a[0] = zero4;
+    a[1] = zero4;
+    a[2] = zero4;
+    any = true;
+    if (!col) continue;
+    const uint32_t mask = clampm[o];
+    const float grgb[3] = {(mask & 1u) ? 0.f : a1.z, (mask & 2u) ? 0.f : a1.w,
+                           (mask & 4u) ? 0.f : a2.x};
+    if (!mf_loaded) {
+      for (int k = 0; k < 3; ++k) mf[k] = (float)(double)prm.means[k * n + i];
+      mf_loaded = true;
+    }
+    const CamDev& c = vt.v[v];
+    float dx = mf[0] - c.campos[0];
+    float dy = mf[1] - c.campos[1];
+    float dz = mf[2] - c.campos[2];
+    const float len = sqrtf(dx * dx + dy * dy + dz * dz);
+    const float inv = 1.0f / len;
+    dx *= inv;
+    dy *= inv;
+    dz *= inv;
+    float Y[16];
+    sh_basis(dx, dy, dz, deg, Y);
+    float w[16];
+#pragma unroll
+    for (int j = 0; j < nb; ++j) {
+      float s = 0.f;
+#pragma unroll
+      for (int ch = 0; ch < 3; ++ch) {
+        g_sh[j * 3 + ch] += Y[j] * grgb[ch];
+        s += prm.sh[(size_t)(j * 3 + ch) * n + i] * grgb[ch];
+      }
+      w[j] = s;
+    }
+    float gx = 0.f, gy = 0.f, gz = 0.f;
+    sh_basis_grad_dot(dx, dy, dz, deg, w, gx, gy, gz);
+    const float dot = gx * dx + gy * dy + gz * dz;
+    gmf[0] += (gx - dx * dot) * inv;
+    gmf[1] += (gy - dy * dot) * inv;
+    gmf[2] += (gz - dz * dot) * inv;
+  }
+  for (int k = 0; k < 3; ++k) g_mu[k] += (double)gmf[k];
+
+  // ---- 3. scale and rotation from dL/dSigma3; opacity
+  double g_ls[3] = {0, 0, 0}, g_q[4] = {0, 0, 0, 0}, g_logit = 0;
+  if (loaded) {
+    Body b;
+    load_body(prm, i, b);
+    const double G[9] = {Gs[0], Gs[1], Gs[2], Gs[1], Gs[3], Gs[4], Gs[2], Gs[4], Gs[5]};
     // Sigma3 = M M^T, M = Rq diag(s)
     double M[9];
     for (int r = 0; r < 3; ++r)
@@ -405,15 +444,15 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(ParamsDev prm, ViewTable
     double gM[9];
     for (int r = 0; r < 3; ++r)
       for (int q = 0; q < 3; ++q)
-        gM[r * 3 + q] = Gs[r * 3 + 0] * M[0 * 3 + q] + Gs[r * 3 + 1] * M[1 * 3 + q] +
-                        Gs[r * 3 + 2] * M[2 * 3 + q];
+        gM[r * 3 + q] = G[r * 3 + 0] * M[0 * 3 + q] + G[r * 3 + 1] * M[1 * 3 + q] +
+                        G[r * 3 + 2] * M[2 * 3 + q];
     double gR[9];
     for (int r = 0; r < 3; ++r)
       for (int q = 0; q < 3; ++q) gR[r * 3 + q] = gM[r * 3 + q] * b.s[q];
     for (int q = 0; q < 3; ++q) {
       const double gsq = gM[0 * 3 + q] * b.Rq[0 * 3 + q] + gM[1 * 3 + q] * b.Rq[1 * 3 + q] +
                          gM[2 * 3 + q] * b.Rq[2 * 3 + q];
-      g_ls[q] += gsq * b.s[q];
+      g_ls[q] = gsq * b.s[q];
     }
     // rotation of the unit quaternion, entry by entry
     const double w = b.qn[0], x = b.qn[1], y = b.qn[2], z = b.qn[3];
@@ -426,10 +465,12 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(ParamsDev prm, ViewTable
     const double gz = 2 * (-2 * z * g[0] - w * g[1] + x * g[2] + w * g[3] - 2 * z * g[4] +
                            y * g[5] + x * g[6] + y * g[7]);
     const double dot = w * gw + x * gx + y * gy + z * gz;
-    g_q[0] += (gw - w * dot) / b.qnorm;
-    g_q[1] += (gx - x * dot) / b.qnorm;
-    g_q[2] += (gy - y * dot) / b.qnorm;
-    g_q[3] += (gz - z * dot) / b.qnorm;
+    g_q[0] = (gw - w * dot) / b.qnorm;
+    g_q[1] = (gx - x * dot) / b.qnorm;
+    g_q[2] = (gy - y * dot) / b.qnorm;
+    g_q[3] = (gz - z * dot) / b.qnorm;
+    const double op = 1.0 / (1.0 + exp(-(double)prm.logits[i]));
+    g_logit = g_op * op * (1.0 - op);
   }
   // write (or add) the gradients; untouched Gaussians get zeros
   const bool add = gout.accumulate != 0;

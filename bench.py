@@ -442,17 +442,18 @@ def main():
 
     # headline: the captured batched step; roofline from the eager run of the same
     # (tuned) configuration, whose per-stage HIP-event times are the same kernels
-    head = res.get("batched_graph") or res["plain"]
+    form = next(k for k in ("batched_graph", "batched", "plain") if k in res)
+    head = res[form]
     eager = res.get("batched") or res["plain"]
-    form = "batched_graph" if "batched_graph" in res else "plain"
     value = head["pixels"] / (head["ms"] * 1e-3) / 1e6
     dom, roof = roofline(eager["stages"], args.steps, n, eager["views"], eager["visible"],
                          eager["K"], eager["pixels"], eager["pairs"])
     roof["traffic"] = (measured_traffic(dom, eager["views"], tune["best"])
                        if args.n is None and args.grid is None and tune is not None else None)
-    if form == "batched_graph":
+    if form != "plain":
+        how = "one hipGraph replay" if form == "batched_graph" else "eager launches"
         wl = (f"kingsnake4m: {n} Gaussians on a seeded 1024^3 blob+noise isosurface, SH3; "
-              f"batched form: 4 views (2x2048^2 + 2x1536^2) per step, one hipGraph replay "
+              f"batched form: 4 views (2x2048^2 + 2x1536^2) per step, {how} "
               f"(projection, sort, persistent/grid blend, loss gradient, backward), tuned "
               f"tile {tune['best']['tile']}, LDS depth {tune['best']['lds_depth']}, "
               f"flags {tune['best']['flags']}")

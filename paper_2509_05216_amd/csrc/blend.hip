@@ -16,12 +16,14 @@
 // (block-wide vote).  The backward walks the list from the tile's last
 // contributor down to its first, recomputing each pixel's transmittance as
 // T * rcp(1 - alpha) from the final value (1 - alpha >= 0.01, so the 1-ulp
-// hardware reciprocal is ample), so no per-pixel list is stored.  Per-pair
-// gradients (9 floats) are reduce-scattered across the wave (two gfx950
-// permlane swaps, then DPP steps inside 16-lane rows: about 28 VALU
-// instructions for all nine sums), added across the workgroup's waves with
-// LDS float atomics and to the per-Gaussian accumulators with one global
-// atomic per component per (tile, Gaussian).
+// hardware reciprocal is ample), so no per-pixel list is stored.  Each pair
+// yields nine per-lane sums (dpow dx, dpow dy, dpow dx^2, dpow dx dy, dpow dy^2,
+// dalpha G and the three colour weights; the conic is applied to the first two
+// once per (tile, Gaussian) when the sums are flushed).  They are
+// reduce-scattered across the wave (two gfx950 permlane swaps, then three DPP
+// steps inside 16-lane rows: about 25 VALU instructions for all nine), added
+// across the workgroup's waves with LDS float atomics and to the per-Gaussian
+// accumulators with one global atomic per component per (tile, Gaussian).
 //
 // Both walks are branch-free per pair (lanes that skip a pair select zeros),
 // keep two slots' LDS operands in flight, and take each slot index from a
@@ -221,10 +223,10 @@ __device__ inline void fwd_tile(Stage<TILE * TILE, DEPTH>& st, const ViewTable& 
       const bool stop = use && Tn < kTMin;
       done = done || stop;
       use = use && !stop;
-      const float w = alpha * T;
-      cr = use ? cr + s.q2.x * w : cr;
-      cg = use ? cg + s.q2.y * w : cg;
-      cb = use ? cb + s.q2.z * w : cb;
+      const float w = use ? alpha * T : 0.f;
+      cr = fmaf(s.q2.x, w, cr);
+      cg = fmaf(s.q2.y, w, cg);
+      cb = fmaf(s.q2.z, w, cb);
       T = use ? Tn : T;
       last = use ? base + (uint32_t)s.j - rg.x + 1u : last;
     };
@@ -301,15 +303,6 @@ __device__ inline float dpp_f(float x, int ctrl) {
   }
 }
 
-// Sum of x over the 16 lanes of each row, in every lane of the row.
-__device__ inline float row_sum16(float x) {
-  x += dpp_f(x, 0xB1);   // quad_perm [1,0,3,2]: pairs l, l^1
-  x += dpp_f(x, 0x4E);   // quad_perm [2,3,0,1]: pairs l, l^2
-  x += dpp_f(x, 0x141);  // row_half_mirror: quad 0 <-> quad 1 within each 8 lanes
-  x += dpp_f(x, 0x128);  // row_ror:8: the two halves of the row
-  return x;
-}
-
 // (a + partner) where lanes 0-31 pair with 32-63: lower lanes get a's sum,
 // upper lanes b's sum.
 __device__ inline float swap32_sum(float a, float b) {
@@ -323,30 +316,44 @@ __device__ inline float swap16_sum(float a, float b) {
   return __uint_as_float(r[0]) + __uint_as_float(r[1]);
 }
 
-// Reduce g[0..8] over the wave and add each sum to part[k] with one LDS atomic.
-// After the xor-32 step lanes 0-31 carry values {0..4} and lanes 32-63 {5..8};
-// after the xor-16 step row r, slot m carries value (r>>1)*5 + 2m + (r&1).
-__device__ inline void wave_reduce_add(const float* g, float* part) {
+// Reduce-scatter of nine per-lane values over the wave.  xor-32 pairs leave
+// five values per lane (g0..g4 in lanes 0-31, g5..g8 in 32-63), xor-16 pairs
+// three (row r holds values base + odd, base + 2 + odd and base + 4, with
+// base = 5 (r >> 1) and odd = r & 1).  Inside a 16-lane row the xor-8 step
+// (row_ror:8) merges the first two, the mirror step of each 8-lane half
+// merges that result with the third, and the quad steps finish: lane 0 of the
+// row then holds the row sum of the first value, lane 8 of the second and
+// lane 4 of the third.  lane_slot() names the value a lane ends up owning.
+__device__ inline int lane_slot(int lane) {
+  const int row = lane >> 4, p = lane & 15;
+  const int base = 5 * (row >> 1), odd = row & 1;
+  if (p == 0) return base + odd;
+  if (p == 8) return base + 2 + odd;
+  if (p == 4 && row == 0) return 4;
+  return -1;
+}
+
+// Adds the wave sums of g[0..8] to part[k] (one LDS atomic per sum); slot is
+// lane_slot(lane).
+__device__ inline void wave_reduce_add(const float* g, float* part, int slot, bool hi8, bool hi4) {
   const float a0 = swap32_sum(g[0], g[5]);
   const float a1 = swap32_sum(g[1], g[6]);
   const float a2 = swap32_sum(g[2], g[7]);
   const float a3 = swap32_sum(g[3], g[8]);
   const float a4 = swap32_sum(g[4], 0.f);
-  const float b0 = row_sum16(swap16_sum(a0, a1));
-  const float b1 = row_sum16(swap16_sum(a2, a3));
-  const float b2 = row_sum16(swap16_sum(a4, 0.f));
-  const int lane = __lane_id();
-  const int row = lane >> 4, m = lane & 15;
-  if (m < 3) {
-    const int hi = row >> 1, odd = row & 1;
-    const int aslot = 2 * m + odd;
-    const bool valid = hi ? (aslot <= 3) : (aslot <= 4);
-    if (valid) {
-      const int k = hi ? 5 + aslot : aslot;
-      const float s = (m == 0) ? b0 : ((m == 1) ? b1 : b2);
-      if (s != 0.f) atomicAdd(&part[k], s);
-    }
-  }
+  const float b0 = swap16_sum(a0, a1);
+  const float b1 = swap16_sum(a2, a3);
+  const float b2 = swap16_sum(a4, 0.f);
+  // xor 8: lanes 0-7 keep b0 and take the partner's b0, lanes 8-15 likewise b1
+  const float k01 = hi8 ? b1 : b0, s01 = hi8 ? b0 : b1;
+  const float c01 = k01 + dpp_f(s01, 0x128);
+  const float c2 = b2 + dpp_f(b2, 0x128);
+  // mirror within 8 lanes: q < 4 keeps c01, q >= 4 keeps c2
+  const float kd = hi4 ? c2 : c01, sd = hi4 ? c01 : c2;
+  float d = kd + dpp_f(sd, 0x141);
+  d += dpp_f(d, 0x4E);  // quad_perm [2,3,0,1]
+  d += dpp_f(d, 0xB1);  // quad_perm [1,0,3,2]
+  if (slot >= 0 && d != 0.f) atomicAdd(&part[slot], d);
 }
 
 template <int TILE, int DEPTH>
@@ -390,8 +397,11 @@ __device__ inline void bwd_tile(BwdSmem<TILE, DEPTH>& sm, const ViewTable& vt, i
     dg = cam.dimg[plane + pix];
     db = cam.dimg[2 * plane + pix];
   }
-  // colour composited behind the current record (starts with T_final * bg)
-  float Sr = T * vt.bg[0], Sg = T * vt.bg[1], Sb = T * vt.bg[2];
+  // D = dL/dout . S, with S the colour composited behind the current record
+  // (it starts as T_final * bg); dL/dalpha needs S only through this product
+  float D = T * (dr * vt.bg[0] + dg * vt.bg[1] + db * vt.bg[2]);
+  const int slot = lane_slot(lane);
+  const bool hi8 = (lane & 8) != 0, hi4 = (lane & 4) != 0;
   // last contributor of the wave and of the tile
   uint32_t m = nc;
 #pragma unroll
@@ -426,7 +436,7 @@ __device__ inline void bwd_tile(BwdSmem<TILE, DEPTH>& sm, const ViewTable& vt, i
       const float alpha = fminf(kAlphaMax, a_raw);
       const bool contrib =
           inside && (uint32_t)(lo + s.j) < nc && !(power > 0.f) && !(alpha < kAlphaMin);
-      if (!__any(contrib)) return;
+      if (__builtin_amdgcn_ballot_w64(contrib) == 0) return;
       // Gradient arithmetic, branch-free: a lane that does not contribute selects
       // zeros, so its nine values are exactly 0 and its state is unchanged.
       // 1 - alpha >= 0.01, so the hardware reciprocal (1 ulp) is safe here.
@@ -434,28 +444,28 @@ __device__ inline void bwd_tile(BwdSmem<TILE, DEPTH>& sm, const ViewTable& vt, i
       const float Tb = T * inv;  // transmittance before this record
       T = contrib ? Tb : T;
       const float w = contrib ? alpha * Tb : 0.f;
-      float dalpha = dr * fmaf(q2.x, Tb, -Sr * inv);
-      dalpha = fmaf(dg, fmaf(q2.y, Tb, -Sg * inv), dalpha);
-      dalpha = fmaf(db, fmaf(q2.z, Tb, -Sb * inv), dalpha);
-      Sr = fmaf(q2.x, w, Sr);
-      Sg = fmaf(q2.y, w, Sg);
-      Sb = fmaf(q2.z, w, Sb);
-      // alpha clamped at its maximum has zero derivative
+      // dL/dalpha = T_before (dL/dout . rgb) - D / (1 - alpha); clamped alpha has
+      // zero derivative
+      const float cdot = fmaf(db, q2.z, fmaf(dg, q2.y, dr * q2.x));
       const bool open = contrib && a_raw <= kAlphaMax;
-      dalpha = open ? dalpha : 0.f;
+      const float dalpha = open ? fmaf(Tb, cdot, -D * inv) : 0.f;
+      D = fmaf(w, cdot, D);
+      // Per-pair sums whose (tile, Gaussian) totals give the screen gradients:
+      // dpow dx, dpow dy (mean, after the conic is applied at the flush),
+      // dpow dx^2, dpow dx dy, dpow dy^2 (conic), dalpha G (opacity), w dL/dout.
       const float dpow = dalpha * alpha;
-      const float hp = -0.5f * dpow;
+      const float ex = dpow * dx, ey = dpow * dy;
       float g[9];
-      g[0] = dpow * fmaf(q0.x, dx, q0.y * dy);
-      g[1] = dpow * fmaf(q0.y, dx, q0.z * dy);
-      g[2] = hp * dx * dx;
-      g[3] = -dpow * dx * dy;
-      g[4] = hp * dy * dy;
+      g[0] = ex;
+      g[1] = ey;
+      g[2] = ex * dx;
+      g[3] = ex * dy;
+      g[4] = ey * dy;
       g[5] = open ? dalpha * G : 0.f;
       g[6] = w * dr;
       g[7] = w * dg;
       g[8] = w * db;
-      wave_reduce_add(g, &part[s.j * 9]);
+      wave_reduce_add(g, &part[s.j * 9], slot, hi8, hi4);
     };
     // two slots in flight: the LDS reads of one overlap the arithmetic of the other
     if (k >= 0) {
@@ -471,9 +481,17 @@ __device__ inline void bwd_tile(BwdSmem<TILE, DEPTH>& sm, const ViewTable& vt, i
     }
     __syncthreads();
     for (int t = threadIdx.x; t < cnt * 9; t += NT) {
-      const float s = part[t];
+      const int j = t / 9, c = t - j * 9;
+      float s = part[t];
+      if (c < 2) {
+        // mean: (A dx + B dy, B dx + C dy) dpow summed = conic applied to the sums
+        const float4 q = st.s0[j];
+        const float e0 = part[j * 9], e1 = part[j * 9 + 1];
+        s = c == 0 ? fmaf(q.x, e0, q.y * e1) : fmaf(q.y, e0, q.z * e1);
+      } else if (c < 5) {
+        s *= c == 3 ? -1.f : -0.5f;  // conic: -dpow dx^2 / 2, -dpow dx dy, -dpow dy^2 / 2
+      }
       if (s != 0.f) {
-        const int j = t / 9, c = t - j * 9;
         // AoS accumulators: the nine components of a (view, Gaussian) are adjacent,
         // so neighbouring lanes' atomics fall in one or two cache lines
         atomicAdd(acc + (size_t)st.sidx[j] * kAccStride + c, s);

@@ -27,10 +27,13 @@
 //
 // Both walks are branch-free per pair (lanes that skip a pair select zeros),
 // keep two slots' LDS operands in flight, and take each slot index from a
-// 64-entry VGPR copy of the wave's list through readlane.  Both kernels
-// evaluate the skip/stop decisions with the same inline, uncontracted code
-// (the library is compiled with -ffp-contract=off), so the backward
-// reproduces the forward's decisions exactly.
+// 64-entry VGPR copy of the wave's list through readlane.  A staged splat
+// carries its conic pre-scaled by -log2(e)/2 (one fused quadratic and one
+// v_exp per pair) and its mean relative to the tile origin.  Both kernels
+// evaluate the skip/stop decisions with the same inline code on the same
+// staged values (the library is compiled with -ffp-contract=off, and the
+// fused operations are explicit), so the backward reproduces the forward's
+// decisions exactly.
 #include "internal.h"
 
 namespace isogs {
@@ -40,12 +43,20 @@ constexpr float kAlphaMin = 1.0f / 255.0f;
 constexpr float kAlphaMax = 0.99f;
 constexpr float kTMin = 1e-4f;
 
-// power = -1/2 (A dx^2 + C dy^2) - B dx dy at pixel (px, py); dx = px + 0.5 - mean_x.
-__device__ inline void pair_eval(float A, float B, float C, int cx, int cy, float fx, float fy,
-                                 int px, int py, float& dx, float& dy, float& power) {
-  dx = (float)(px - cx) + fx;
-  dy = (float)(py - cy) + fy;
-  power = -0.5f * (A * dx * dx + C * dy * dy) - B * dx * dy;
+// Staged form of a splat: the conic scaled so that one fused quadratic gives
+// log2 of the Gaussian factor,
+//   p2 = log2(e) * power = a dx^2 + b dx dy + c dy^2,
+//   (a, b, c) = -log2(e) (A / 2, B, C / 2),
+// and the mean relative to the tile origin, so dx = (pixel x - tile x0) - mx'.
+constexpr float kLog2e = 1.4426950408889634f;
+constexpr float kLn2 = 0.6931471805599453f;
+
+// p2 and the offsets (dx, dy) of a pixel (tile-relative integer coordinates
+// rx, ry as floats) from a staged splat; exp2(p2) is the Gaussian factor.
+__device__ inline float pair_eval(float4 q, float2 m, float rx, float ry, float& dx, float& dy) {
+  dx = rx - m.x;
+  dy = ry - m.y;
+  return fmaf(fmaf(q.y, dy, q.x * dx), dx, (q.z * dy) * dy);
 }
 
 // Conservative box of the alpha >= 1/255 region: (mean_x, mean_y, half_w, half_h);
@@ -78,7 +89,9 @@ __device__ inline bool box_misses(float4 b, int bx0, int by0) {
 template <int NT, int DEPTH>
 struct Stage {
   static constexpr int NW = NT / 64;
-  float4 s0[DEPTH], s1[DEPTH], s2[DEPTH];
+  float4 s0[DEPTH];  // scaled conic (a, b, c), opacity
+  float2 s1[DEPTH];  // mean relative to the tile origin
+  float4 s2[DEPTH];  // rgb
   uint32_t sidx[DEPTH];
   uint16_t list[NW][DEPTH];
   uint32_t chunk[NW][DEPTH / 64 + 1];
@@ -99,8 +112,9 @@ __device__ inline void stage_batch(Stage<TILE * TILE, DEPTH>& st, const uint32_t
     const uint32_t idx = tval[base + t];
     const float4 q0 = splat[(size_t)idx * 3 + 0], q1 = splat[(size_t)idx * 3 + 1];
     st.sidx[t] = idx;
-    st.s0[t] = q0;
-    st.s1[t] = q1;
+    st.s0[t] = make_float4(q0.x * (-0.5f * kLog2e), q0.y * -kLog2e, q0.z * (-0.5f * kLog2e), q0.w);
+    st.s1[t] = make_float2((float)(__float_as_int(q1.x) - tile_x0) - q1.z,
+                           (float)(__float_as_int(q1.y) - tile_y0) - q1.w);
     st.s2[t] = splat[(size_t)idx * 3 + 2];
     const float4 b = splat_box(q0, q1);
 #pragma unroll
@@ -170,8 +184,9 @@ struct WaveList {
 // Operands of one staged splat, read from LDS (same address in every lane).
 struct Slot {
   int j;
-  float4 q0, q1;
-  float3 q2;
+  float4 q0;  // scaled conic, opacity
+  float2 m;   // tile-relative mean
+  float3 q2;  // rgb
 };
 
 template <int NT, int DEPTH>
@@ -179,7 +194,7 @@ __device__ inline Slot load_slot(const Stage<NT, DEPTH>& st, int j) {
   Slot s;
   s.j = j;
   s.q0 = st.s0[j];
-  s.q1 = st.s1[j];
+  s.m = st.s1[j];
   s.q2 = make_float3(st.s2[j].x, st.s2[j].y, st.s2[j].z);
   return s;
 }
@@ -200,6 +215,7 @@ __device__ inline void fwd_tile(Stage<TILE * TILE, DEPTH>& st, const ViewTable& 
   Layout<TILE>::pixel(tile_x, tile_y, px, py, bx0, by0);
   const int wave = threadIdx.x / 64;
   const bool inside = px < cam.W && py < cam.H;
+  const float rx = (float)(px - tile_x * TILE), ry = (float)(py - tile_y * TILE);
   const uint2 rg = ranges[gt];
   float T = 1.f, cr = 0.f, cg = 0.f, cb = 0.f;
   uint32_t last = 0;
@@ -213,12 +229,10 @@ __device__ inline void fwd_tile(Stage<TILE * TILE, DEPTH>& st, const ViewTable& 
     WaveList<NT, DEPTH> wl(st, wave);
     // Branch-free front-to-back step; a lane that has stopped keeps its state.
     auto step = [&](const Slot& s) {
-      const float4 q0 = s.q0, q1 = s.q1;
-      float dx, dy, power;
-      pair_eval(q0.x, q0.y, q0.z, __float_as_int(q1.x), __float_as_int(q1.y), q1.z, q1.w, px, py,
-                dx, dy, power);
-      const float alpha = fminf(kAlphaMax, q0.w * __expf(power));
-      bool use = !done && !(power > 0.f) && !(alpha < kAlphaMin);
+      float dx, dy;
+      const float p2 = pair_eval(s.q0, s.m, rx, ry, dx, dy);
+      const float alpha = fminf(kAlphaMax, s.q0.w * __builtin_amdgcn_exp2f(p2));
+      bool use = !done && !(p2 > 0.f) && !(alpha < kAlphaMin);
       const float Tn = T * (1.f - alpha);
       const bool stop = use && Tn < kTMin;
       done = done || stop;
@@ -383,6 +397,7 @@ __device__ inline void bwd_tile(BwdSmem<TILE, DEPTH>& sm, const ViewTable& vt, i
   int px, py, bx0, by0;
   Layout<TILE>::pixel(tile_x, tile_y, px, py, bx0, by0);
   const bool inside = px < cam.W && py < cam.H;
+  const float rx = (float)(px - tile_x * TILE), ry = (float)(py - tile_y * TILE);
   const uint2 rg = ranges[gt];
   const int lane = __lane_id(), wave = threadIdx.x / 64;
 
@@ -425,17 +440,15 @@ __device__ inline void bwd_tile(BwdSmem<TILE, DEPTH>& sm, const ViewTable& vt, i
     while (k >= 0 && lo + wl.at(k) >= wave_n) --k;
     // One pair (this lane's pixel, slot s) of the reverse walk.
     auto pair = [&](const Slot& s) {
-      const float4 q0 = s.q0, q1 = s.q1;
       const float3 q2 = s.q2;
-      // the skip decisions are the forward's, from the same uncontracted expressions
-      float dx, dy, power;
-      pair_eval(q0.x, q0.y, q0.z, __float_as_int(q1.x), __float_as_int(q1.y), q1.z, q1.w, px, py,
-                dx, dy, power);
-      const float G = __expf(power);
-      const float a_raw = q0.w * G;
+      // the skip decisions are the forward's, from the same expressions
+      float dx, dy;
+      const float p2 = pair_eval(s.q0, s.m, rx, ry, dx, dy);
+      const float G = __builtin_amdgcn_exp2f(p2);
+      const float a_raw = s.q0.w * G;
       const float alpha = fminf(kAlphaMax, a_raw);
       const bool contrib =
-          inside && (uint32_t)(lo + s.j) < nc && !(power > 0.f) && !(alpha < kAlphaMin);
+          inside && (uint32_t)(lo + s.j) < nc && !(p2 > 0.f) && !(alpha < kAlphaMin);
       if (__builtin_amdgcn_ballot_w64(contrib) == 0) return;
       // Gradient arithmetic, branch-free: a lane that does not contribute selects
       // zeros, so its nine values are exactly 0 and its state is unchanged.
@@ -486,8 +499,9 @@ __device__ inline void bwd_tile(BwdSmem<TILE, DEPTH>& sm, const ViewTable& vt, i
       if (c < 2) {
         // mean: (A dx + B dy, B dx + C dy) dpow summed = conic applied to the sums
         const float4 q = st.s0[j];
+        const float A = q.x * (-2.f * kLn2), B = q.y * -kLn2, C = q.z * (-2.f * kLn2);
         const float e0 = part[j * 9], e1 = part[j * 9 + 1];
-        s = c == 0 ? fmaf(q.x, e0, q.y * e1) : fmaf(q.y, e0, q.z * e1);
+        s = c == 0 ? fmaf(A, e0, B * e1) : fmaf(B, e0, C * e1);
       } else if (c < 5) {
         s *= c == 3 ? -1.f : -0.5f;  // conic: -dpow dx^2 / 2, -dpow dx dy, -dpow dy^2 / 2
       }

@@ -163,23 +163,15 @@ struct Layout {
   }
 };
 
-// A wave's compacted slot list, read 64 entries at a time into one VGPR; the
-// entry at a wave-uniform position comes back as a scalar through readlane, so
-// the walk needs no LDS round trip per slot for its index.
-template <int NT, int DEPTH>
-struct WaveList {
-  const uint16_t* row;
-  int lv = 0, chunk = -1;
-  __device__ WaveList(const Stage<NT, DEPTH>& st, int wave) : row(st.list[wave]) {}
-  __device__ int at(int kk) {
-    const int c = kk >> 6;
-    if (c != chunk) {
-      chunk = c;
-      lv = row[min(c * 64 + (int)__lane_id(), DEPTH - 1)];
-    }
-    return __builtin_amdgcn_readlane(lv, kk & 63);
-  }
-};
+// A wave's compacted slot list is walked 64 entries at a time: one LDS read
+// puts entries [c0, c0 + 64) in a VGPR (one per lane) and the entry at a
+// wave-uniform position comes back as a scalar through readlane, so the walk
+// needs no LDS round trip per slot for its index.
+__device__ inline int list_chunk(const uint16_t* row, int c0, int depth) {
+  return row[min(c0 + (int)__lane_id(), depth - 1)];
+}
+
+__device__ inline int list_at(int chunk, int kk) { return __builtin_amdgcn_readlane(chunk, kk & 63); }
 
 // Operands of one staged splat, read from LDS (same address in every lane).
 struct Slot {
@@ -226,7 +218,6 @@ __device__ inline void fwd_tile(Stage<TILE * TILE, DEPTH>& st, const ViewTable& 
     stage_batch<TILE, DEPTH>(st, tval, splat, base, cnt, tile_x * TILE, tile_y * TILE);
     const int nw = __builtin_amdgcn_readfirstlane((int)st.count[wave]);
     if (nw == 0 || !__any(!done)) continue;
-    WaveList<NT, DEPTH> wl(st, wave);
     // Branch-free front-to-back step; a lane that has stopped keeps its state.
     auto step = [&](const Slot& s) {
       float dx, dy;
@@ -244,15 +235,26 @@ __device__ inline void fwd_tile(Stage<TILE * TILE, DEPTH>& st, const ViewTable& 
       T = use ? Tn : T;
       last = use ? base + (uint32_t)s.j - rg.x + 1u : last;
     };
-    // two slots in flight: the LDS reads of one overlap the arithmetic of the other
-    Slot a = load_slot(st, wl.at(0));
-    for (int k = 0; k < nw; k += 2) {
-      const bool two = k + 1 < nw;
-      const Slot b = load_slot(st, wl.at(two ? k + 1 : k));
-      step(a);
-      a = load_slot(st, wl.at(min(k + 2, nw - 1)));
-      if (two) step(b);
-      if (!__any(!done)) break;
+    const uint16_t* row = st.list[wave];
+    bool all_done = false;
+    for (int c0 = 0; c0 < nw && !all_done; c0 += 64) {
+      const int chunk = list_chunk(row, c0, DEPTH);
+      const int n = min(64, nw - c0);
+      // two slots in flight: the LDS reads of one overlap the arithmetic of the other
+      Slot a = load_slot(st, list_at(chunk, 0));
+      int kk = 0;
+      for (; kk + 1 < n; kk += 2) {
+        const Slot b = load_slot(st, list_at(chunk, kk + 1));
+        step(a);
+        a = load_slot(st, list_at(chunk, min(kk + 2, n - 1)));
+        step(b);
+        if ((kk & 6) == 6 && !__any(!done)) {  // every 8 slots
+          all_done = true;
+          break;
+        }
+      }
+      if (!all_done && kk < n) step(a);  // odd tail
+      all_done = all_done || !__any(!done);
     }
   }
   if (inside) {
@@ -435,9 +437,19 @@ __device__ inline void bwd_tile(BwdSmem<TILE, DEPTH>& sm, const ViewTable& vt, i
     stage_batch<TILE, DEPTH>(st, tval, splat, rg.x + (uint32_t)lo, cnt, tile_x * TILE,
                              tile_y * TILE);
     // walk this wave's overlapping slots from the back, below its last contributor
-    WaveList<NT, DEPTH> wl(st, wave);
-    int k = __builtin_amdgcn_readfirstlane((int)st.count[wave]) - 1;
-    while (k >= 0 && lo + wl.at(k) >= wave_n) --k;
+    // entries of this wave's list below its last contributor: the list is
+    // ascending, so they are a prefix, counted by ballots over its chunks
+    const uint16_t* row = st.list[wave];
+    const int cw = __builtin_amdgcn_readfirstlane((int)st.count[wave]);
+    int nuse = 0;
+    if (lo < wave_n) {
+      for (int c0 = 0; c0 < cw; c0 += 64) {
+        const int e = c0 + (int)__lane_id();
+        const bool below = e < cw && lo + (int)row[min(e, DEPTH - 1)] < wave_n;
+        nuse += (int)__popcll(__ballot(below));
+      }
+    }
+    int k = nuse - 1;
     // One pair (this lane's pixel, slot s) of the reverse walk.
     auto pair = [&](const Slot& s) {
       const float3 q2 = s.q2;
@@ -482,15 +494,23 @@ __device__ inline void bwd_tile(BwdSmem<TILE, DEPTH>& sm, const ViewTable& vt, i
     };
     // two slots in flight: the LDS reads of one overlap the arithmetic of the other
     if (k >= 0) {
-      Slot a = load_slot(st, wl.at(k));
-      while (k >= 1) {
-        const Slot b = load_slot(st, wl.at(k - 1));
-        pair(a);
-        a = load_slot(st, wl.at(max(k - 2, 0)));
-        pair(b);
-        k -= 2;
+      int c0 = k & ~63;
+      int chunk = list_chunk(row, c0, DEPTH);
+      if ((k & 1) == 0) {  // odd count: the top entry alone, then pairs (k, k - 1)
+        pair(load_slot(st, list_at(chunk, k)));
+        --k;
+        if (k >= 0 && (k & 63) == 63) chunk = list_chunk(row, c0 -= 64, DEPTH);
       }
-      if (k == 0) pair(a);
+      // k is odd here, so k and k - 1 share a chunk; two slots in flight
+      Slot a = load_slot(st, list_at(chunk, max(k, 0)));
+      while (k >= 1) {
+        const Slot b = load_slot(st, list_at(chunk, k - 1));
+        pair(a);
+        k -= 2;
+        if (k >= 0 && (k & 63) == 63) chunk = list_chunk(row, c0 -= 64, DEPTH);
+        a = load_slot(st, list_at(chunk, max(k, 0)));
+        pair(b);
+      }
     }
     __syncthreads();
     for (int t = threadIdx.x; t < cnt * 9; t += NT) {

@@ -3,91 +3,164 @@
 //
 // SSIM uses an 11 x 11 Gaussian window (sigma 1.5, separable, weights summing
 // to one), C1 = 0.01^2, C2 = 0.03^2, zero padding, averaged over pixels and
-// channels.  Two LDS-tiled passes per view (16 x 16 output pixels per block,
-// a 26 x 26 halo tile): the first forms the five local moments by separable
-// filtering and writes, per pixel, the partials g1 = dS/dmu_x, g2 = dS/dE[x^2]
-// and g3 = dS/dE[xy]; the second filters those maps (the window is symmetric,
-// so the zero-padded correlation is its own adjoint) and combines them with
-// the L1 term:  dL/dx = s [(1 - lambda) sign(x - y)
-//                          - lambda (w*g1 + 2 x w*g2 + y w*g3)],  s = 1/(3 H W V).
-// Loss sums are reduced per block into float64 partials and summed by a final
-// single-block kernel, so the loss value is deterministic.
+// channels.  Two LDS-tiled passes per view and channel (32 x 32 output pixels
+// per 256-thread block, a 42 x 42 halo tile): the first forms the five local
+// moments by separable filtering and writes, per pixel, the partials
+// g1 = dS/dmu_x, g2 = dS/dE[x^2] and g3 = dS/dE[xy]; the second filters those
+// maps (the window is symmetric, so the zero-padded correlation is its own
+// adjoint) and combines them with the L1 term:
+//   dL/dx = s [(1 - lambda) sign(x - y) - lambda (w*g1 + 2 x w*g2 + y w*g3)],
+//   s = 1/(3 H W V).
+// Horizontal taps share w x between the moments and use explicit fused
+// multiply-adds; in the vertical pass each thread produces four consecutive
+// rows of one column from 14 LDS rows.  Loss sums are reduced per block into
+// float64 partials and summed by a final single-block kernel, so the loss
+// value is deterministic.
 #include "internal.h"
 
 namespace isogs {
 namespace {
 
-constexpr int kB = 16;           // output tile side
+constexpr int kT = 32;           // output tile side
 constexpr int kR = 5;            // window radius
-constexpr int kS = kB + 2 * kR;  // 26: halo tile side
+constexpr int kN = 2 * kR + 1;   // taps
+constexpr int kH = kT + 2 * kR;  // 42: halo tile side
+constexpr int kP = kH + 1;       // padded LDS row of the halo tile
+constexpr int kQ = kT + 1;       // padded LDS row of the horizontal pass
+constexpr int kRows = 4;         // output rows per thread in the vertical pass
 constexpr float kC1 = 0.01f * 0.01f;
 constexpr float kC2 = 0.03f * 0.03f;
 
 struct Win {
-  float w[2 * kR + 1];
+  float w[kN];
 };
+
+constexpr int kLoads = (kH * kH + 255) / 256;  // halo elements per thread
+
+// Halo element t of the tile whose top-left halo pixel is (ox, oy): whether it
+// lies in the image, and an in-image offset to read (clamped, so every load is
+// valid; the value is replaced by zero padding when outside).
+__device__ inline bool halo_inside(int t, int ox, int oy, int W, int H) {
+  const int gx = ox + t % kH, gy = oy + t / kH;
+  return gx >= 0 && gx < W && gy >= 0 && gy < H;
+}
+
+__device__ inline size_t halo_offset(int t, int ox, int oy, int W, int H) {
+  const int gx = min(max(ox + t % kH, 0), W - 1), gy = min(max(oy + t / kH, 0), H - 1);
+  return (size_t)gy * W + gx;
+}
+
+// Thread layout of the vertical pass: column c, rows r0 .. r0 + 3.
+__device__ inline void vert_slot(int& c, int& r0) {
+  c = threadIdx.x % kT;
+  r0 = (threadIdx.x / kT) * kRows;
+}
+
+// Vertical filtering of NM moment maps held in LDS (hq[m][row][col]) for the
+// four rows of this thread: out[o][m] = sum_i w[i] hq[m][r0 + o + i][c].
+template <int NM>
+__device__ inline void vert_filter(const float (*hq)[kH][kQ], const Win& win, int c, int r0,
+                                   float (*out)[NM]) {
+#pragma unroll
+  for (int o = 0; o < kRows; ++o)
+#pragma unroll
+    for (int m = 0; m < NM; ++m) out[o][m] = 0.f;
+#pragma unroll
+  for (int i = 0; i < kN + kRows - 1; ++i) {
+#pragma unroll
+    for (int m = 0; m < NM; ++m) {
+      const float v = hq[m][r0 + i][c];
+#pragma unroll
+      for (int o = 0; o < kRows; ++o)
+        if (i - o >= 0 && i - o < kN) out[o][m] = fmaf(win.w[i - o], v, out[o][m]);
+    }
+  }
+}
 
 __global__ __launch_bounds__(256) void k_ssim_fwd(const float* __restrict__ x,
                                                   const float* __restrict__ y, int W, int H,
                                                   Win win, float* __restrict__ gmap,
                                                   double* __restrict__ part) {
-  __shared__ float sx[kS][kS], sy[kS][kS];
-  __shared__ float hq[5][kS][kB];
+  __shared__ float sx[kH][kP], sy[kH][kP];
+  __shared__ float hq[5][kH][kQ];
   const int ch = blockIdx.z;
   const size_t plane = (size_t)W * H;
   const float* xc = x + ch * plane;
   const float* yc = y + ch * plane;
-  const int ox = blockIdx.x * kB - kR, oy = blockIdx.y * kB - kR;
-  for (int t = threadIdx.x; t < kS * kS; t += 256) {
-    const int r = t / kS, c = t % kS;
-    const int gx = ox + c, gy = oy + r;
-    const bool in = gx >= 0 && gx < W && gy >= 0 && gy < H;
-    sx[r][c] = in ? xc[(size_t)gy * W + gx] : 0.f;
-    sy[r][c] = in ? yc[(size_t)gy * W + gx] : 0.f;
-  }
-  __syncthreads();
-  for (int t = threadIdx.x; t < kS * kB; t += 256) {
-    const int r = t / kB, c = t % kB;
-    float a0 = 0, a1 = 0, a2 = 0, a3 = 0, a4 = 0;
+  const int ox = blockIdx.x * kT - kR, oy = blockIdx.y * kT - kR;
+  {
+    // every halo load is issued before the first LDS store (clamped addresses,
+    // zero outside the image), so their latencies overlap
+    float vx[kLoads], vy[kLoads];
 #pragma unroll
-    for (int i = 0; i < 2 * kR + 1; ++i) {
-      const float xv = sx[r][c + i], yv = sy[r][c + i], w = win.w[i];
-      a0 += w * xv;
-      a1 += w * yv;
-      a2 += w * xv * xv;
-      a3 += w * yv * yv;
-      a4 += w * xv * yv;
+    for (int q = 0; q < kLoads; ++q) {
+      const size_t o = halo_offset(threadIdx.x + q * 256, ox, oy, W, H);
+      vx[q] = xc[o];
+      vy[q] = yc[o];
     }
-    hq[0][r][c] = a0; hq[1][r][c] = a1; hq[2][r][c] = a2; hq[3][r][c] = a3; hq[4][r][c] = a4;
+#pragma unroll
+    for (int q = 0; q < kLoads; ++q) {
+      const int t = threadIdx.x + q * 256;
+      if (t < kH * kH) {
+        const bool in = halo_inside(t, ox, oy, W, H);
+        sx[t / kH][t % kH] = in ? vx[q] : 0.f;
+        sy[t / kH][t % kH] = in ? vy[q] : 0.f;
+      }
+    }
   }
   __syncthreads();
-  const int r = threadIdx.x / kB, c = threadIdx.x % kB;
-  const int gx = blockIdx.x * kB + c, gy = blockIdx.y * kB + r;
-  float mx = 0, my = 0, exx = 0, eyy = 0, exy = 0;
+  for (int t = threadIdx.x; t < kH * kT; t += 256) {
+    const int r = t / kT, c = t % kT;
+    float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f, a4 = 0.f;
 #pragma unroll
-  for (int i = 0; i < 2 * kR + 1; ++i) {
-    const float w = win.w[i];
-    mx += w * hq[0][r + i][c];
-    my += w * hq[1][r + i][c];
-    exx += w * hq[2][r + i][c];
-    eyy += w * hq[3][r + i][c];
-    exy += w * hq[4][r + i][c];
+    for (int i = 0; i < kN; ++i) {
+      const float xv = sx[r][c + i], yv = sy[r][c + i];
+      const float wx = win.w[i] * xv, wy = win.w[i] * yv;
+      a0 += wx;
+      a1 += wy;
+      a2 = fmaf(wx, xv, a2);
+      a3 = fmaf(wy, yv, a3);
+      a4 = fmaf(wx, yv, a4);
+    }
+    hq[0][r][c] = a0;
+    hq[1][r][c] = a1;
+    hq[2][r][c] = a2;
+    hq[3][r][c] = a3;
+    hq[4][r][c] = a4;
   }
+  __syncthreads();
+  int c, r0;
+  vert_slot(c, r0);
+  float mom[kRows][5];
+  vert_filter<5>(hq, win, c, r0, mom);
   double l1 = 0.0, ss = 0.0;
-  if (gx < W && gy < H) {
-    const float sxx = exx - mx * mx, syy = eyy - my * my, sxy = exy - mx * my;
-    const float A1 = 2.f * mx * my + kC1, A2 = 2.f * sxy + kC2;
-    const float B1 = mx * mx + my * my + kC1, B2 = sxx + syy + kC2;
-    const float S = (A1 * A2) / (B1 * B2);
-    const float g1 = S * (2.f * my / A1 - 2.f * my / A2 - 2.f * mx / B1 + 2.f * mx / B2);
-    const float g2 = -S / B2;
-    const float g3 = 2.f * S / A2;
-    const size_t pix = (size_t)gy * W + gx;
-    gmap[(0 * 3 + ch) * plane + pix] = g1;
-    gmap[(1 * 3 + ch) * plane + pix] = g2;
-    gmap[(2 * 3 + ch) * plane + pix] = g3;
-    l1 = fabs((double)sx[r + kR][c + kR] - (double)sy[r + kR][c + kR]);
-    ss = (double)S;
+  const int gx = blockIdx.x * kT + c;
+#pragma unroll
+  for (int o = 0; o < kRows; ++o) {
+    const int gy = blockIdx.y * kT + r0 + o;
+    if (gx < W && gy < H) {
+      const float mx = mom[o][0], my = mom[o][1];
+      const float sxx = mom[o][2] - mx * mx, syy = mom[o][3] - my * my;
+      const float sxy = mom[o][4] - mx * my;
+      const float A1 = 2.f * mx * my + kC1, A2 = 2.f * sxy + kC2;
+      const float B1 = mx * mx + my * my + kC1, B2 = sxx + syy + kC2;
+      // With P = 1/(B1 B2) and S = A1 A2 P:
+      //   dS/dmu_x = 2 P my (A2 - A1) + 2 S mx (1/B2 - 1/B1),
+      //   dS/dE[x^2] = -S / B2,  dS/dE[xy] = 2 A1 P,
+      // so only B1 >= C1 and B2 >= C2 are inverted (A2 = 2 sigma_xy + C2 may vanish).
+      const float iB1 = __builtin_amdgcn_rcpf(B1), iB2 = __builtin_amdgcn_rcpf(B2);
+      const float Pb = iB1 * iB2;
+      const float S = (A1 * A2) * Pb;
+      const float g1 = 2.f * (my * (A2 - A1) * Pb + S * mx * (iB2 - iB1));
+      const float g2 = -S * iB2;
+      const float g3 = 2.f * A1 * Pb;
+      const size_t pix = (size_t)gy * W + gx;
+      gmap[(0 * 3 + ch) * plane + pix] = g1;
+      gmap[(1 * 3 + ch) * plane + pix] = g2;
+      gmap[(2 * 3 + ch) * plane + pix] = g3;
+      l1 += fabs((double)sx[r0 + o + kR][c + kR] - (double)sy[r0 + o + kR][c + kR]);
+      ss += (double)S;
+    }
   }
   // block reduction of the two sums
   __shared__ double red[2][4];
@@ -114,48 +187,60 @@ __global__ __launch_bounds__(256) void k_ssim_bwd(const float* __restrict__ x,
                                                   Win win, const float* __restrict__ gmap,
                                                   float lambda, float scale,
                                                   float* __restrict__ dl) {
-  __shared__ float sg[3][kS][kS];
-  __shared__ float hq[3][kS][kB];
+  __shared__ float sg[3][kH][kP];
+  __shared__ float hq[3][kH][kQ];
   const int ch = blockIdx.z;
   const size_t plane = (size_t)W * H;
-  const int ox = blockIdx.x * kB - kR, oy = blockIdx.y * kB - kR;
-  for (int t = threadIdx.x; t < kS * kS; t += 256) {
-    const int r = t / kS, c = t % kS;
-    const int gx = ox + c, gy = oy + r;
-    const bool in = gx >= 0 && gx < W && gy >= 0 && gy < H;
-    const size_t pix = (size_t)gy * W + gx;
+  const int ox = blockIdx.x * kT - kR, oy = blockIdx.y * kT - kR;
+  {
+    float v[3][kLoads];
 #pragma unroll
-    for (int m = 0; m < 3; ++m) sg[m][r][c] = in ? gmap[(m * 3 + ch) * plane + pix] : 0.f;
-  }
-  __syncthreads();
-  for (int t = threadIdx.x; t < kS * kB; t += 256) {
-    const int r = t / kB, c = t % kB;
-    float a0 = 0, a1 = 0, a2 = 0;
+    for (int q = 0; q < kLoads; ++q) {
+      const size_t o = halo_offset(threadIdx.x + q * 256, ox, oy, W, H);
 #pragma unroll
-    for (int i = 0; i < 2 * kR + 1; ++i) {
-      const float w = win.w[i];
-      a0 += w * sg[0][r][c + i];
-      a1 += w * sg[1][r][c + i];
-      a2 += w * sg[2][r][c + i];
+      for (int m = 0; m < 3; ++m) v[m][q] = gmap[(m * 3 + ch) * plane + o];
     }
-    hq[0][r][c] = a0; hq[1][r][c] = a1; hq[2][r][c] = a2;
+#pragma unroll
+    for (int q = 0; q < kLoads; ++q) {
+      const int t = threadIdx.x + q * 256;
+      if (t < kH * kH) {
+        const bool in = halo_inside(t, ox, oy, W, H);
+#pragma unroll
+        for (int m = 0; m < 3; ++m) sg[m][t / kH][t % kH] = in ? v[m][q] : 0.f;
+      }
+    }
   }
   __syncthreads();
-  const int r = threadIdx.x / kB, c = threadIdx.x % kB;
-  const int gx = blockIdx.x * kB + c, gy = blockIdx.y * kB + r;
-  if (gx >= W || gy >= H) return;
-  float f1 = 0, f2 = 0, f3 = 0;
+  for (int t = threadIdx.x; t < kH * kT; t += 256) {
+    const int r = t / kT, c = t % kT;
+    float a0 = 0.f, a1 = 0.f, a2 = 0.f;
 #pragma unroll
-  for (int i = 0; i < 2 * kR + 1; ++i) {
-    const float w = win.w[i];
-    f1 += w * hq[0][r + i][c];
-    f2 += w * hq[1][r + i][c];
-    f3 += w * hq[2][r + i][c];
+    for (int i = 0; i < kN; ++i) {
+      const float w = win.w[i];
+      a0 = fmaf(w, sg[0][r][c + i], a0);
+      a1 = fmaf(w, sg[1][r][c + i], a1);
+      a2 = fmaf(w, sg[2][r][c + i], a2);
+    }
+    hq[0][r][c] = a0;
+    hq[1][r][c] = a1;
+    hq[2][r][c] = a2;
   }
-  const size_t pix = ch * plane + (size_t)gy * W + gx;
-  const float xv = x[pix], yv = y[pix];
-  const float sgn = (xv > yv) ? 1.f : ((xv < yv) ? -1.f : 0.f);
-  dl[pix] = scale * ((1.f - lambda) * sgn - lambda * (f1 + 2.f * xv * f2 + yv * f3));
+  __syncthreads();
+  int c, r0;
+  vert_slot(c, r0);
+  float f[kRows][3];
+  vert_filter<3>(hq, win, c, r0, f);
+  const int gx = blockIdx.x * kT + c;
+  if (gx >= W) return;
+#pragma unroll
+  for (int o = 0; o < kRows; ++o) {
+    const int gy = blockIdx.y * kT + r0 + o;
+    if (gy >= H) break;
+    const size_t pix = ch * plane + (size_t)gy * W + gx;
+    const float xv = x[pix], yv = y[pix];
+    const float sgn = (xv > yv) ? 1.f : ((xv < yv) ? -1.f : 0.f);
+    dl[pix] = scale * ((1.f - lambda) * sgn - lambda * (f[o][0] + 2.f * xv * f[o][1] + yv * f[o][2]));
+  }
 }
 
 struct LossRed {
@@ -232,13 +317,13 @@ gs_status launch_loss(Ctx* ctx, const float* const* x, const float* const* y, co
                       hipStream_t s) {
   Win win;
   {
-    double g[2 * kR + 1], sum = 0.0;
-    for (int i = 0; i < 2 * kR + 1; ++i) {
+    double g[kN], sum = 0.0;
+    for (int i = 0; i < kN; ++i) {
       const double d = i - kR;
       g[i] = exp(-(d * d) / (2.0 * 1.5 * 1.5));
       sum += g[i];
     }
-    for (int i = 0; i < 2 * kR + 1; ++i) win.w[i] = (float)(g[i] / sum);
+    for (int i = 0; i < kN; ++i) win.w[i] = (float)(g[i] / sum);
   }
   if (ctx->loss_scratch == nullptr) ctx->loss_scratch = new LossScratch();
   LossScratch& ls = loss_scratch(ctx);
@@ -248,7 +333,7 @@ gs_status launch_loss(Ctx* ctx, const float* const* x, const float* const* y, co
   for (int v = 0; v < nv; ++v) {
     const size_t plane = (size_t)W[v] * H[v];
     if (plane > max_plane) max_plane = plane;
-    const int nbx = (W[v] + kB - 1) / kB, nby = (H[v] + kB - 1) / kB;
+    const int nbx = (W[v] + kT - 1) / kT, nby = (H[v] + kT - 1) / kT;
     lr.nblk[v] = nbx * nby * 3;
     lr.off[v] = (long long)total_blocks;
     lr.inv_count[v] = 1.0 / (3.0 * (double)plane);
@@ -260,7 +345,7 @@ gs_status launch_loss(Ctx* ctx, const float* const* x, const float* const* y, co
   if (st != GS_OK) return st;
   double* part2 = (double*)ls.part.p + 2 * total_blocks;
   for (int v = 0; v < nv; ++v) {
-    const dim3 grid((W[v] + kB - 1) / kB, (H[v] + kB - 1) / kB, 3);
+    const dim3 grid((W[v] + kT - 1) / kT, (H[v] + kT - 1) / kT, 3);
     hipLaunchKernelGGL(k_ssim_fwd, grid, dim3(256), 0, s, x[v], y[v], W[v], H[v], win,
                        (float*)ls.gmap.p, (double*)ls.part.p + 2 * lr.off[v]);
     GS_LAUNCHED("ssim_fwd");

@@ -192,7 +192,7 @@ def test_screen_space_accumulators(P, ctx):
 # ------------------------------------------------------------------ loss, adam
 def test_loss_and_gradient(P, ctx):
     rng = np.random.default_rng(9)
-    sizes = [(64, 48), (37, 29)]
+    sizes = [(64, 48), (37, 29), (161, 97)]  # one tile, a ragged tile, 6 x 4 tiles with tails
     xs = [rng.random((3, H, W)) for W, H in sizes]
     ys = [np.clip(x + rng.normal(0, 0.1, x.shape), 0, 1) for x in xs]
     cams = [P.camera(np.eye(3), [0, 0, 0], 50, 50, W / 2, H / 2, W, H) for W, H in sizes]

@@ -181,12 +181,21 @@ __global__ __launch_bounds__(kThreads) void k_radix_hist(const uint32_t* __restr
   }
 }
 
+// One pass of the stable LSD sort.  Each block ranks its 4096 elements by
+// digit (wave ballots, stable), places them in LDS in block-local digit order,
+// and writes them out so that consecutive threads store consecutive addresses
+// of one digit's run: the global writes are coalesced.
+static_assert(kThreads == kRadix, "one thread per digit in the offset scan");
+
 __global__ __launch_bounds__(kThreads) void k_radix_scatter(
     const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin, uint32_t* __restrict__ kout,
     uint32_t* __restrict__ vout, uint32_t n_max, const uint32_t* d_n, int shift, uint32_t nblocks,
     const uint32_t* __restrict__ hist_scanned) {
   __shared__ uint32_t cnt[kWaves][kRadix];
-  __shared__ uint32_t gofs[kRadix];
+  __shared__ uint32_t gofs[kRadix];    // global position of local index 0 of digit d's run
+  __shared__ uint32_t lstart[kRadix];  // block-local start of digit d
+  __shared__ uint64_t scan_tmp[kWaves];
+  __shared__ uint32_t sk[kChunk], sv[kChunk];
   const int wave = threadIdx.x / 64, lane = __lane_id();
   for (int d = threadIdx.x; d < kWaves * kRadix; d += kThreads) (&cnt[0][0])[d] = 0;
   const uint32_t n = load_n(n_max, d_n);
@@ -223,14 +232,20 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(
     rank[j] = old + (uint32_t)__popcll(peers & lt);
   }
   __syncthreads();
-  for (int d = threadIdx.x; d < kRadix; d += kThreads) {
+  {
+    // thread d: wave prefixes of digit d, the block-local start of d and its
+    // global position (unsigned wrap-around is intended in gofs - start)
+    const int d = threadIdx.x;
     uint32_t run = 0;
     for (int w = 0; w < kWaves; ++w) {
       const uint32_t c = cnt[w][d];
       cnt[w][d] = run;
       run += c;
     }
-    gofs[d] = hist_scanned[(size_t)d * nblocks + blockIdx.x];
+    uint64_t total;
+    const uint32_t start = (uint32_t)block_exclusive_scan(run, scan_tmp, total);
+    lstart[d] = start;
+    gofs[d] = hist_scanned[(size_t)d * nblocks + blockIdx.x] - start;
   }
   __syncthreads();
 #pragma unroll
@@ -238,10 +253,18 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(
     const uint32_t i = base + j * 64 + lane;
     if (i < n) {
       const uint32_t d = (key[j] >> shift) & 0xffu;
-      const uint32_t pos = gofs[d] + cnt[wave][d] + rank[j];
-      kout[pos] = key[j];
-      vout[pos] = val[j];
+      const uint32_t lp = lstart[d] + cnt[wave][d] + rank[j];
+      sk[lp] = key[j];
+      sv[lp] = val[j];
     }
+  }
+  __syncthreads();
+  const uint32_t nloc = min((uint32_t)kChunk, n - blockIdx.x * (uint32_t)kChunk);
+  for (uint32_t t = threadIdx.x; t < nloc; t += kThreads) {
+    const uint32_t k = sk[t];
+    const uint32_t pos = gofs[(k >> shift) & 0xffu] + t;
+    kout[pos] = k;
+    vout[pos] = sv[t];
   }
 }
 

@@ -89,8 +89,9 @@ __device__ inline bool box_misses(float4 b, int bx0, int by0) {
 template <int NT, int DEPTH>
 struct Stage {
   static constexpr int NW = NT / 64;
+  // 16 bytes per slot in every array, so one shifted index addresses all three
   float4 s0[DEPTH];  // scaled conic (a, b, c), opacity
-  float2 s1[DEPTH];  // mean relative to the tile origin
+  float4 s1[DEPTH];  // mean relative to the tile origin (x, y), unused (z, w)
   float4 s2[DEPTH];  // rgb
   uint32_t sidx[DEPTH];
   uint16_t list[NW][DEPTH];
@@ -113,8 +114,8 @@ __device__ inline void stage_batch(Stage<TILE * TILE, DEPTH>& st, const uint32_t
     const float4 q0 = splat[(size_t)idx * 3 + 0], q1 = splat[(size_t)idx * 3 + 1];
     st.sidx[t] = idx;
     st.s0[t] = make_float4(q0.x * (-0.5f * kLog2e), q0.y * -kLog2e, q0.z * (-0.5f * kLog2e), q0.w);
-    st.s1[t] = make_float2((float)(__float_as_int(q1.x) - tile_x0) - q1.z,
-                           (float)(__float_as_int(q1.y) - tile_y0) - q1.w);
+    st.s1[t] = make_float4((float)(__float_as_int(q1.x) - tile_x0) - q1.z,
+                           (float)(__float_as_int(q1.y) - tile_y0) - q1.w, 0.f, 0.f);
     st.s2[t] = splat[(size_t)idx * 3 + 2];
     const float4 b = splat_box(q0, q1);
 #pragma unroll
@@ -186,7 +187,7 @@ __device__ inline Slot load_slot(const Stage<NT, DEPTH>& st, int j) {
   Slot s;
   s.j = j;
   s.q0 = st.s0[j];
-  s.m = st.s1[j];
+  s.m = make_float2(st.s1[j].x, st.s1[j].y);
   s.q2 = make_float3(st.s2[j].x, st.s2[j].y, st.s2[j].z);
   return s;
 }
@@ -240,20 +241,29 @@ __device__ inline void fwd_tile(Stage<TILE * TILE, DEPTH>& st, const ViewTable& 
     for (int c0 = 0; c0 < nw && !all_done; c0 += 64) {
       const int chunk = list_chunk(row, c0, DEPTH);
       const int n = min(64, nw - c0);
-      // two slots in flight: the LDS reads of one overlap the arithmetic of the other
+      // two slots in flight (the LDS reads of one overlap the arithmetic of the
+      // other), four per iteration
       Slot a = load_slot(st, list_at(chunk, 0));
       int kk = 0;
-      for (; kk + 1 < n; kk += 2) {
-        const Slot b = load_slot(st, list_at(chunk, kk + 1));
+      for (; kk + 3 < n; kk += 4) {
+        Slot b = load_slot(st, list_at(chunk, kk + 1));
         step(a);
-        a = load_slot(st, list_at(chunk, min(kk + 2, n - 1)));
+        a = load_slot(st, list_at(chunk, kk + 2));
         step(b);
-        if ((kk & 6) == 6 && !__any(!done)) {  // every 8 slots
+        b = load_slot(st, list_at(chunk, kk + 3));
+        step(a);
+        a = load_slot(st, list_at(chunk, min(kk + 4, n - 1)));
+        step(b);
+        if ((kk & 4) != 0 && !__any(!done)) {  // every 8 slots
           all_done = true;
           break;
         }
       }
-      if (!all_done && kk < n) step(a);  // odd tail
+      for (; kk < n && !all_done; ++kk) {  // up to three left; a holds entry kk
+        const Slot b = load_slot(st, list_at(chunk, min(kk + 1, n - 1)));
+        step(a);
+        a = b;
+      }
       all_done = all_done || !__any(!done);
     }
   }
@@ -534,8 +544,10 @@ __device__ inline void bwd_tile(BwdSmem<TILE, DEPTH>& sm, const ViewTable& vt, i
   }
 }
 
+// The backward is held to 80 VGPRs (six waves per SIMD; the allocation
+// granule is eight registers, so one register more would cost a wave).
 template <int TILE, int DEPTH>
-__global__ __launch_bounds__(TILE* TILE) void k_blend_bwd(ViewTable vt,
+__global__ __launch_bounds__(TILE* TILE) __attribute__((amdgpu_waves_per_eu(6))) void k_blend_bwd(ViewTable vt,
                                                           const uint2* __restrict__ ranges,
                                                           const uint32_t* __restrict__ tval,
                                                           const float4* __restrict__ splat,
@@ -547,7 +559,7 @@ __global__ __launch_bounds__(TILE* TILE) void k_blend_bwd(ViewTable vt,
 }
 
 template <int TILE, int DEPTH>
-__global__ __launch_bounds__(TILE* TILE) void k_blend_bwd_persistent(
+__global__ __launch_bounds__(TILE* TILE) __attribute__((amdgpu_waves_per_eu(6))) void k_blend_bwd_persistent(
     ViewTable vt, const uint2* __restrict__ ranges, const uint32_t* __restrict__ tval,
     const float4* __restrict__ splat, const float* __restrict__ finalT,
     const uint32_t* __restrict__ ncon, float* __restrict__ acc, const uint32_t* __restrict__ order,

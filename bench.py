@@ -72,6 +72,9 @@ def parse():
     ap.add_argument("--only", choices=["all", "batched", "plain"], default="all")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--workload", choices=["kingsnake4m", "miranda18m"], default="kingsnake4m",
+                    help="kingsnake4m: 4M Gaussians, 2x2048^2 + 2x1536^2 batched and 2048^2 plain "
+                         "(the headline); miranda18m: 18M Gaussians, a batch of two 4096^2 views")
     ap.add_argument("--no-graph", action="store_true",
                     help="skip the graph-captured forms (e.g. for counter collection)")
     ap.add_argument("--config", default=None,
@@ -348,19 +351,24 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
     t0 = time.perf_counter()
-    scene = gsscenes.make_scene("kingsnake4m", n=args.n, G=args.grid)
+    scene = gsscenes.make_scene(args.workload, n=args.n, G=args.grid, progress=log)
     n = scene.params["means"].shape[1]
     log(f"scene: {n} Gaussians in {time.perf_counter() - t0:.1f}s")
     ctx = P.Context(0)
     params = P.Params.from_numpy(scene.params)
-    sizes = [2048, 2048, 1536, 1536]
-    all_cams = P.orbit_cameras(16, 2.5, 60.0, 2048, 2048)
+    if args.workload == "miranda18m":
+        sizes, stride = [4096, 4096], 8
+        args.only = "batched"  # the 18M workload is the two-view batch only
+        args.no_serve = True
+    else:
+        sizes, stride = [2048, 2048, 1536, 1536], 4
+    all_cams = P.orbit_cameras(16, 2.5, 60.0, sizes[0], sizes[0])
     cams = []
     for i, s in enumerate(sizes):
-        c = all_cams[i * 4]
+        c = all_cams[i * stride]
         d = P.camera_to_dict(c)
-        cams.append(P.camera(d["R"], d["t"], d["fx"] * s / 2048, d["fy"] * s / 2048, s / 2, s / 2,
-                             s, s))
+        cams.append(P.camera(d["R"], d["t"], d["fx"] * s / sizes[0], d["fy"] * s / sizes[0],
+                             s / 2, s / 2, s, s))
     cams_d = [P.camera_to_dict(c) for c in cams]
     t0 = time.perf_counter()
     targets_np = make_targets(scene, cams_d)
@@ -387,14 +395,15 @@ def main():
                                                   torch, flags=best["flags"])
         st, pairs, vis = frame_counts(frame, n, torch)
         res["batched"] = dict(ms=ms, stages=stages, K=st["n_records"], pixels=st["n_pixels"],
-                              pairs=pairs, visible=vis, views=4, loss=loss)
+                              pairs=pairs, visible=vis, views=len(cams), loss=loss)
         log(f"batched (eager, tuned): {ms:.2f} ms/step, K={st['n_records']}, pairs={pairs}")
         frame.release()
     if args.only in ("all", "batched") and not args.no_graph:
         # the captured step: fwd+bwd, then fwd+bwd+Adam
         gms, rec, cap, gloss = run_graph(P, ctx, params, cams, targets, args.steps, args.warmup,
                                          best, False, torch)
-        res["batched_graph"] = dict(ms=gms, K=rec, capacity=cap, pixels=st["n_pixels"], views=4,
+        res["batched_graph"] = dict(ms=gms, K=rec, capacity=cap, pixels=st["n_pixels"],
+                                    views=len(cams),
                                     loss=gloss, visible=vis, pairs=pairs, stages={})
         log(f"batched (graph): {gms:.2f} ms/step")
         pa = P.Params(*(t.clone() for t in params.tensors()), params.sh_degree)
@@ -412,6 +421,14 @@ def main():
                             pairs=pairs, visible=vis, views=1, loss=loss)
         log(f"plain: {ms:.2f} ms/step, K={st['n_records']}, pairs={pairs}")
         frame.release()
+    # device memory of the training step (before the Adam and copy-probe legs allocate
+    # their own buffers): the library's buffers (current and high-water), the caller's
+    # tensors (torch's high-water mark) and the device's use as the driver reports it
+    lib_now, lib_peak = ctx.memory()
+    free_b, total_b = torch.cuda.mem_get_info()
+    memory = {"library_bytes": lib_now, "library_peak_bytes": lib_peak,
+              "torch_peak_bytes": torch.cuda.max_memory_allocated(),
+              "device_used_bytes": total_b - free_b, "device_total_bytes": total_b}
     # Adam over all Gaussians, timed on its own
     grads = params.zeros_like()
     m, v = params.zeros_like(), params.zeros_like()
@@ -450,15 +467,21 @@ def main():
                          eager["K"], eager["pixels"], eager["pairs"])
     roof["traffic"] = (measured_traffic(dom, eager["views"], tune["best"])
                        if args.n is None and args.grid is None and tune is not None else None)
+    if args.workload == "miranda18m":
+        field = "seeded 2048^3 mixing-layer isosurface"
+        views_desc = "2 views of 4096^2"
+    else:
+        field = "seeded 1024^3 blob+noise isosurface"
+        views_desc = "4 views (2x2048^2 + 2x1536^2)"
     if form != "plain":
         how = "one hipGraph replay" if form == "batched_graph" else "eager launches"
-        wl = (f"kingsnake4m: {n} Gaussians on a seeded 1024^3 blob+noise isosurface, SH3; "
-              f"batched form: 4 views (2x2048^2 + 2x1536^2) per step, {how} "
+        wl = (f"{args.workload}: {n} Gaussians on a {field}, SH3; "
+              f"batched form: {views_desc} per step, {how} "
               f"(projection, sort, persistent/grid blend, loss gradient, backward), tuned "
               f"tile {tune['best']['tile']}, LDS depth {tune['best']['lds_depth']}, "
               f"flags {tune['best']['flags']}")
     else:
-        wl = f"kingsnake4m: {n} Gaussians, SH3; plain form: one 2048^2 view per step"
+        wl = f"{args.workload}: {n} Gaussians, SH3; plain form: one {sizes[0]}^2 view per step"
     out = {
         "metric": METRIC, "value": round(value, 3), "unit": "Mpix/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(head["ms"], 3),
@@ -467,6 +490,7 @@ def main():
         "config": {"workload": wl, "views_per_step": head["views"],
                    "pixels_per_step": head["pixels"], "gaussians": n},
         "gaussians_per_s": round(n * head["views"] / (head["ms"] * 1e-3), 1),
+        "memory": memory,
         "roofline": roof,
         "forms": {k: {"ms_per_step": round(r["ms"], 3),
                       "mpix_per_s": round(r["pixels"] / (r["ms"] * 1e-3) / 1e6, 3),

@@ -62,40 +62,40 @@ def make_field(name):
     raise KeyError(name)
 
 
-def make_scene(name, n=None, G=None):
+def make_scene(name, n=None, G=None, progress=None):
     idx = PRESETS.index(name)
     _, r_pts, r_par, _, _ = _streams(idx)
     fld, G0 = make_field(name)
     G = G0 if G is None else G
     if name == "tiny":
         n = 10_000 if n is None else n
-        pts, h = sample_points(fld, G, n, r_pts)
+        pts, h = sample_points(fld, G, n, r_pts, progress=progress)
         params = synth_params(r_par, pts, sh_degree=0, log_scale=np.log(h),
                               opacity_logit=0.1)
         views = ViewSet(8, 2.5, 60.0, [(256, 256)])
     elif name == "iso1m":
         n = 1_000_000 if n is None else n
-        pts, h = sample_points(fld, G, n, r_pts)
+        pts, h = sample_points(fld, G, n, r_pts, progress=progress)
         params = synth_params(r_par, pts, sh_degree=3, log_scale_range=(-5.0, -3.0),
                               random_quats=True, opacity_logit=0.1, sh_std=0.1)
         views = ViewSet(128, 2.5, 60.0, [(1024, 1024)])
     elif name == "kingsnake4m":
         n = 4_000_000 if n is None else n
-        pts, h = sample_points(fld, G, n, r_pts)
+        pts, h = sample_points(fld, G, n, r_pts, progress=progress)
         params = synth_params(r_par, pts, sh_degree=3, log_scale=np.log(h),
                               log_scale_jitter=0.5, random_quats=True,
                               opacity_logit=0.1, sh_std=0.1)
         views = ViewSet(4, 2.5, 60.0, [(2048, 2048), (2048, 2048), (1536, 1536), (1536, 1536)])
     elif name == "miranda18m":
         n = 18_000_000 if n is None else n
-        pts, h = sample_points(fld, G, n, r_pts)
+        pts, h = sample_points(fld, G, n, r_pts, progress=progress)
         params = synth_params(r_par, pts, sh_degree=3, log_scale=np.log(h),
                               log_scale_jitter=0.5, random_quats=True,
                               opacity_logit=0.1, sh_std=0.1)
         views = ViewSet(2, 2.5, 60.0, [(4096, 4096)])
     elif name == "serve":
         n = 100_000 if n is None else n
-        pts, h = sample_points(fld, G, n, r_pts)
+        pts, h = sample_points(fld, G, n, r_pts, progress=progress)
         params = synth_params(r_par, pts, sh_degree=3, log_scale=np.log(h),
                               log_scale_jitter=0.5, random_quats=True,
                               opacity_logit_range=(0.0, 4.0), sh_std=0.1)

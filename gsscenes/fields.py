@@ -121,10 +121,19 @@ class MixingLayer:
         s = 0.5 / self.delta / np.cosh(z / self.delta) ** 2
         return dz * s[:, None]
 
+    def z_support(self):
+        """Heights outside which f - 1/2 has one sign on every (x, y): |eta + noise| <= bound."""
+        b = float(np.abs(self.a).sum() + np.abs(self.noise.a).sum())
+        return -b, b
+
     def slab(self, xs, z):
-        X, Y = np.meshgrid(xs, xs)
-        eta = self._eta(X, Y)
-        return 0.5 + 0.5 * np.tanh((z + eta + self.noise.slab(xs, z)) / self.delta)
+        # eta does not depend on z: evaluate it once per grid
+        key = (xs.shape[0], float(xs[0]), float(xs[-1]))
+        if getattr(self, "_eta_key", None) != key:
+            X, Y = np.meshgrid(xs, xs)
+            self._eta_grid = self._eta(X, Y)
+            self._eta_key = key
+        return 0.5 + 0.5 * np.tanh((z + self._eta_grid + self.noise.slab(xs, z)) / self.delta)
 
 
 def blob_field(rng, n_blobs, center_half, w_lo, w_hi, noise=None):

@@ -12,12 +12,22 @@ from __future__ import annotations
 import numpy as np
 
 
-def edge_crossings(field, G, iso=0.5, max_points=None, rng=None):
+def edge_crossings(field, G, iso=0.5, max_points=None, rng=None, progress=None):
     xs = np.linspace(-1.0, 1.0, G)
     h = xs[1] - xs[0]
     pts = []
     prev = None
-    for k in range(G):
+    k0, k1 = 0, G - 1
+    if hasattr(field, "z_support"):
+        # planes beyond the support have one sign everywhere and no crossings, nor
+        # do the z-edges between two of them; keep one such plane on each side
+        lo, hi = field.z_support()
+        inside = np.nonzero((xs >= lo) & (xs <= hi))[0]
+        if inside.size:
+            k0, k1 = max(0, int(inside[0]) - 1), min(G - 1, int(inside[-1]) + 1)
+    for k in range(k0, k1 + 1):
+        if progress is not None and (k - k0) % 128 == 0:
+            progress(f"isosurface: plane {k - k0} of {k1 - k0 + 1}")
         cur = field.slab(xs, xs[k]) - iso                 # (y, x)
         # x-edges inside the plane
         s = cur[:, :-1] * cur[:, 1:] < 0
@@ -39,9 +49,9 @@ def edge_crossings(field, G, iso=0.5, max_points=None, rng=None):
     return np.concatenate(pts, 0), h
 
 
-def sample_points(field, G, n, rng, iso=0.5):
+def sample_points(field, G, n, rng, iso=0.5, progress=None):
     """n seeded points on the iso level set (float64, shape (n, 3)), and h."""
-    cand, h = edge_crossings(field, G, iso)
+    cand, h = edge_crossings(field, G, iso, progress=progress)
     m = cand.shape[0]
     if m == 0:
         raise ValueError("field has no crossings of the isovalue on this grid")

@@ -38,7 +38,16 @@ FLOP_PAIR_BWD = 68
 # (profiles/hbm_traffic_kingsnake4m.md), one entry per measured launch configuration and
 # valid only while the kernel source is unchanged: when the source hash no longer matches,
 # or the timed configuration was not measured, the figure is null.
-MEASURED_TRAFFIC = []
+MEASURED_TRAFFIC = [
+    {"kernel": "blend_bwd", "views": 4, "tile": 16, "lds_depth": 256, "flags": 3,
+     "source": "paper_2509_05216_amd/csrc/blend.hip",
+     "sha256": "b236a7eeb55dc03880d3d5ea60eebd765564d88da4ebbebe057e6d1270c50ee6",
+     "read_bytes": 3160.2e6, "write_bytes": 932.5e6},
+    {"kernel": "blend_bwd", "views": 4, "tile": 16, "lds_depth": 128, "flags": 3,
+     "source": "paper_2509_05216_amd/csrc/blend.hip",
+     "sha256": "b236a7eeb55dc03880d3d5ea60eebd765564d88da4ebbebe057e6d1270c50ee6",
+     "read_bytes": 3139.8e6, "write_bytes": 932.5e6},
+]
 
 
 def measured_traffic(kernel, views, render):
@@ -467,6 +476,17 @@ def main():
                          eager["K"], eager["pixels"], eager["pairs"])
     roof["traffic"] = (measured_traffic(dom, eager["views"], tune["best"])
                        if args.n is None and args.grid is None and tune is not None else None)
+    # whole-step fraction of the HBM roofline: the compulsory bytes of every stage
+    # (the algorithmic model above) over the captured step's time, against the
+    # copy probe's achievable bandwidth and the published peak
+    step_bytes = sum(algorithmic(st_, n, eager["views"], eager["visible"], eager["K"],
+                                 eager["pixels"], eager["pairs"])[0]
+                     for st_ in ("project", "depth_sort", "scan", "emit", "tile_sort", "ranges",
+                                 "blend_fwd", "loss", "blend_bwd", "project_bwd"))
+    step_gbs = step_bytes / (head["ms"] * 1e-3) / 1e9
+    step_hbm = {"algorithmic_bytes": int(step_bytes), "ms": round(head["ms"], 4),
+                "GBps": round(step_gbs, 1), "frac_of_probe": round(step_gbs / probe_gbs, 4),
+                "frac_of_peak": round(step_gbs / HBM_PEAK_GBS, 4)}
     if args.workload == "miranda18m":
         field = "seeded 2048^3 mixing-layer isosurface"
         views_desc = "2 views of 4096^2"
@@ -491,6 +511,7 @@ def main():
                    "pixels_per_step": head["pixels"], "gaussians": n},
         "gaussians_per_s": round(n * head["views"] / (head["ms"] * 1e-3), 1),
         "memory": memory,
+        "step_hbm": step_hbm,
         "roofline": roof,
         "forms": {k: {"ms_per_step": round(r["ms"], 3),
                       "mpix_per_s": round(r["pixels"] / (r["ms"] * 1e-3) / 1e6, 3),

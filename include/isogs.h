@@ -138,9 +138,15 @@ typedef enum {
   GS_EXPORT_FINAL_T = 3,    /* float[n_pixels]: transmittance left after blending */
   GS_EXPORT_N_CONTRIB = 4,  /* uint32[n_pixels]: position + 1 of the last contributor */
   GS_EXPORT_SCREEN_GRADS = 5, /* float[n_views][n][12]: dL/d(m_x, m_y, A, B, C, opacity, r, g, b), 3 pad */
-  GS_EXPORT_SPLATS = 6,     /* float[n_views][n][12]: A, B, C, o, mx, my, -, -, r, g, b, depth */
-  GS_EXPORT_RECTS = 7       /* uint32[n_views][n][2]: tile x0 | y0 << 16, x1 | y1 << 16
+  GS_EXPORT_SPLATS = 6,     /* float[n_views][n][12]: conic A, B, C, opacity; floor(mean x),
+                               floor(mean y) as int32 bits, 0.5 - frac(mean x), 0.5 - frac(mean y);
+                               r, g, b; half-widths of the conservative alpha >= 1/255 box as two
+                               fp16 (x in the low 16 bits, y in the high; negative when the splat
+                               can never pass the alpha test).  Only touched entries are defined. */
+  GS_EXPORT_RECTS = 7,      /* uint32[n_views][n][2]: tile x0 | y0 << 16, x1 | y1 << 16
                                (x1 < x0 when the Gaussian touches no tile) */
+  GS_EXPORT_DEPTHS = 8      /* uint32[n_views][n]: float32 camera depth bits of touched entries,
+                               0xffffffff for untouched */
 } gs_export;
 
 /* ------------------------------------------------------------------ core */
@@ -156,6 +162,10 @@ const char* gs_version(void);
  * memory the library allocates for its own scratch (0 = no cap).  Fails with
  * GS_ERR_UNSUPPORTED on a device that is not gfx950. */
 gs_status gs_ctx_create(int device, size_t mem_budget, gs_ctx** out);
+/* Destroy a context.  Frames, step graphs and render servers created on it hold
+ * it: while any of them is alive the call only marks the context, and its last
+ * release (gs_frame_release, gs_step_graph_destroy, gs_server_destroy) frees it.
+ * No other call may use the context after this one. */
 void gs_ctx_destroy(gs_ctx* ctx);
 /* Bytes of device scratch currently held by the context and its frames. */
 gs_status gs_ctx_memory(gs_ctx* ctx, size_t* in_use, size_t* peak);

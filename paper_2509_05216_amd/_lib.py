@@ -19,7 +19,7 @@ GS_ERR = {
 }
 
 EXPORT = {"keys": 0, "values": 1, "ranges": 2, "final_T": 3, "n_contrib": 4,
-          "screen_grads": 5, "splats": 6, "rects": 7}
+          "screen_grads": 5, "splats": 6, "rects": 7, "depths": 8}
 
 
 class IsogsError(RuntimeError):

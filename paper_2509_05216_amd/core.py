@@ -186,6 +186,9 @@ class Frame:
         elif what == "rects":
             out = torch.empty(st["n_views"] * n * 2, dtype=torch.int32, device=device)
             count = None
+        elif what == "depths":
+            out = torch.empty(st["n_views"] * n, dtype=torch.int32, device=device)
+            count = None
         else:
             raise KeyError(what)
         if count == 0:
@@ -234,6 +237,7 @@ def render_fwd(ctx, params, cams, images=None, *, tile=16, lds_depth=256, bg=(0.
     o = _opts(tile, lds_depth, bg, flags)
     L.check(L.lib().gs_render_fwd(ctx.handle, params.abi(), _cam_array(cams), len(cams), pa,
                                   C.byref(o), C.byref(frame.handle), _stream(stream)))
+    frame.ctx = ctx  # the frame is released before its context is
     return images, frame
 
 

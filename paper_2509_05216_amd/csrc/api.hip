@@ -306,6 +306,44 @@ static gs_status set_device(Ctx* ctx) {
 
 using namespace isogs;
 
+namespace isogs {
+
+// Frees a context (its events, loss scratch and host state) once nothing holds it.
+static void ctx_free(gs_ctx* ctx) {
+  (void)hipSetDevice(ctx->device);
+  (void)hipDeviceSynchronize();
+  free_loss_scratch(ctx);
+  (void)timing_collect(ctx);
+  for (int i = 0; i < ctx->n_free; ++i) (void)hipEventDestroy(ctx->free_events[i]);
+  delete[] ctx->free_events;
+  delete[] ctx->pending;
+  delete ctx;
+}
+
+void ctx_retain(Ctx* ctx) {
+  std::lock_guard<std::mutex> lk(ctx->life_mutex);
+  ++ctx->dependents;
+}
+
+void ctx_release(Ctx* ctx) {
+  bool now;
+  {
+    std::lock_guard<std::mutex> lk(ctx->life_mutex);
+    now = --ctx->dependents == 0 && ctx->destroy_requested;
+  }
+  if (now) ctx_free(static_cast<gs_ctx*>(ctx));
+}
+
+// A frame's buffers, the frame and its hold on the context.
+static void frame_delete(gs_frame* fr) {
+  Ctx* ctx = fr->ctx;
+  frame_free(fr);
+  delete fr;
+  ctx_release(ctx);
+}
+
+}  // namespace isogs
+
 extern "C" {
 
 const char* gs_last_error(void) { return g_err; }
@@ -350,14 +388,13 @@ gs_status gs_ctx_create(int device, size_t mem_budget, gs_ctx** out) {
 
 void gs_ctx_destroy(gs_ctx* ctx) {
   if (ctx == nullptr) return;
-  (void)hipSetDevice(ctx->device);
-  (void)hipDeviceSynchronize();
-  free_loss_scratch(ctx);
-  (void)timing_collect(ctx);
-  for (int i = 0; i < ctx->n_free; ++i) (void)hipEventDestroy(ctx->free_events[i]);
-  delete[] ctx->free_events;
-  delete[] ctx->pending;
-  delete ctx;
+  bool now;
+  {
+    std::lock_guard<std::mutex> lk(ctx->life_mutex);
+    ctx->destroy_requested = true;
+    now = ctx->dependents == 0;
+  }
+  if (now) isogs::ctx_free(ctx);
 }
 
 gs_status gs_ctx_set_timing(gs_ctx* ctx, int32_t enable) {
@@ -523,6 +560,7 @@ gs_status gs_render_fwd(gs_ctx* ctx, gs_params params, const gs_camera* cams, in
       return GS_ERR_NOMEM;
     }
     fr->ctx = ctx;
+    ctx_retain(ctx);
   } else if (fr->ctx != ctx) {
     set_error("gs_render_fwd: frame belongs to another context");
     return GS_ERR_INVALID;
@@ -540,15 +578,15 @@ gs_status gs_render_fwd(gs_ctx* ctx, gs_params params, const gs_camera* cams, in
   st = build_views(f, cams, n_views, images, bg);
   if (st == GS_OK) st = frame_buffers(f);
   if (st != GS_OK) {
-    if (fresh) {
-      frame_free(fr);
-      delete fr;
-    }
+    if (fresh) frame_delete(fr);
     return st;
   }
   if (!f.acc_zeroed) {
     st = launch_fill_u32(f.acc.p, 0u, (size_t)f.views * kAccStride * (size_t)f.n, s);
-    if (st != GS_OK) return st;
+    if (st != GS_OK) {
+      if (fresh) frame_delete(fr);
+      return st;
+    }
     f.acc_zeroed = true;
   }
   *state = fr;
@@ -861,6 +899,14 @@ gs_status gs_frame_export(gs_frame* frame, int32_t what, int32_t view, void* dst
         need = n * 8;
       }
       break;
+    case GS_EXPORT_DEPTHS:
+      src = f.dkey.p;
+      need = (size_t)f.views * n * 4;
+      if (view >= 0) {
+        off = (size_t)view * n * 4;
+        need = n * 4;
+      }
+      break;
     default:
       set_error("gs_frame_export: unknown export %d", what);
       return GS_ERR_INVALID;
@@ -878,8 +924,7 @@ void gs_frame_release(gs_frame* frame) {
   if (frame == nullptr) return;
   (void)hipSetDevice(frame->ctx->device);
   (void)hipDeviceSynchronize();
-  frame_free(frame);
-  delete frame;
+  frame_delete(frame);
 }
 
 }  // extern "C"

@@ -4,10 +4,10 @@
 // One workgroup per tile, one pixel per thread (TILE x TILE threads).  Each
 // wave owns an 8 x 8 block of the tile.  The tile's records are staged
 // through LDS in batches of DEPTH splats; every lane of a wave reads the same
-// LDS address (broadcast).  When a splat is staged its loader also computes
-// the axis-aligned box outside which alpha < 1/255 for certain (the ellipse
-// power >= -ln(255 o), widened by a safety margin) and tests it against the
-// tile's 8 x 8 wave blocks; a ballot/popcount compaction then gives every wave
+// LDS address (broadcast).  When a splat is staged its loader also tests the
+// axis-aligned box outside which alpha < 1/255 for certain (the ellipse power
+// >= -ln(255 o), widened by a safety margin; computed once per splat by the
+// projection) against the tile's 8 x 8 wave blocks; a ballot/popcount compaction then gives every wave
 // the ordered list of staged splats that can touch its block, and the wave
 // walks only that list.  Skipped pairs would be rejected by the alpha test
 // anyway, so results are unchanged and most of the per-pair work disappears.
@@ -59,20 +59,22 @@ __device__ inline float pair_eval(float4 q, float2 m, float rx, float ry, float&
   return fmaf(fmaf(q.y, dy, q.x * dx), dx, (q.z * dy) * dy);
 }
 
-// Conservative box of the alpha >= 1/255 region: (mean_x, mean_y, half_w, half_h);
-// half_w < 0 when the splat can never pass the alpha test.
-__device__ inline float4 splat_box(float4 q0, float4 q1) {
-  const float A = q0.x, B = q0.y, C = q0.z, o = q0.w;
+// Conservative box of the alpha >= 1/255 region, (mean_x, mean_y, half_w, half_h),
+// from a splat record: the projection stored the half-widths (fp16, rounded
+// up) in the fourth word of the colour quad; half_w < 0 when the splat can
+// never pass the alpha test.
+__device__ inline float half_lo(uint32_t u) {
+  const uint16_t b = (uint16_t)(u & 0xffffu);
+  _Float16 h;
+  __builtin_memcpy(&h, &b, 2);
+  return (float)h;
+}
+
+__device__ inline float4 splat_box(float4 q1, float4 q2) {
   const float mx = (float)__float_as_int(q1.x) + 0.5f - q1.z;
   const float my = (float)__float_as_int(q1.y) + 0.5f - q1.w;
-  const float lim = o * 255.0f;
-  // determinant in float64: the float32 conic of an elongated splat loses digits here
-  const double det = (double)A * (double)C - (double)B * (double)B;
-  if (!(lim >= 1.0f) || !(det > 0.0)) return make_float4(mx, my, -1.f, -1.f);
-  const double c2 = 2.0 * ((double)logf(lim) + 1e-3);  // bound of dx^T Q dx, with margin
-  const float hw = (float)(sqrt(c2 * (double)C / det) * 1.01 + 1e-2);
-  const float hh = (float)(sqrt(c2 * (double)A / det) * 1.01 + 1e-2);
-  return make_float4(mx, my, hw, hh);
+  const uint32_t hb = __float_as_uint(q2.w);
+  return make_float4(mx, my, half_lo(hb), half_lo(hb >> 16));
 }
 
 // True when the box misses the 8 x 8 block whose first pixel is (bx0, by0).
@@ -112,12 +114,13 @@ __device__ inline void stage_batch(Stage<TILE * TILE, DEPTH>& st, const uint32_t
   if (t < cnt) {
     const uint32_t idx = tval[base + t];
     const float4 q0 = splat[(size_t)idx * 3 + 0], q1 = splat[(size_t)idx * 3 + 1];
+    const float4 q2 = splat[(size_t)idx * 3 + 2];
     st.sidx[t] = idx;
     st.s0[t] = make_float4(q0.x * (-0.5f * kLog2e), q0.y * -kLog2e, q0.z * (-0.5f * kLog2e), q0.w);
     st.s1[t] = make_float4((float)(__float_as_int(q1.x) - tile_x0) - q1.z,
                            (float)(__float_as_int(q1.y) - tile_y0) - q1.w, 0.f, 0.f);
-    st.s2[t] = splat[(size_t)idx * 3 + 2];
-    const float4 b = splat_box(q0, q1);
+    st.s2[t] = q2;  // rgb; the walks do not read .w (the packed box)
+    const float4 b = splat_box(q1, q2);
 #pragma unroll
     for (int w = 0; w < NW; ++w)
       if (!box_misses(b, tile_x0 + (w % BPR) * 8, tile_y0 + (w / BPR) * 8)) mask |= 1u << w;

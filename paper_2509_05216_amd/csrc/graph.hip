@@ -159,6 +159,7 @@ gs_status gs_step_graph_create(gs_ctx* ctx, const gs_step_desc* desc, gs_graph**
     return GS_ERR_NOMEM;
   }
   g->ctx = ctx;
+  ctx_retain(ctx);
   g->desc = *desc;
   g->nv = desc->n_views;
   g->slack = desc->capacity_slack >= 1.05 ? desc->capacity_slack : 1.25;
@@ -273,7 +274,9 @@ void gs_step_graph_destroy(gs_graph* g) {
   if (g->frame != nullptr) gs_frame_release(g->frame);
   if (g->cstream != nullptr) (void)hipStreamDestroy(g->cstream);
   if (g->pinned != nullptr) (void)hipHostFree(g->pinned);
+  Ctx* ctx = g->ctx;
   delete g;
+  ctx_release(ctx);
 }
 
 // ------------------------------------------------------------------ autotune

@@ -150,8 +150,15 @@ struct Ctx {
   int n_free = 0, cap_free = 0;
   double stage_ms[ST_COUNT] = {0};
   long long stage_count[ST_COUNT] = {0};
+  // lifetime: frames, step graphs and render servers hold the context; a
+  // destroy request while any of them lives is carried out by the last release
+  std::mutex life_mutex;
+  int dependents = 0;
+  bool destroy_requested = false;
 };
 
+void ctx_retain(Ctx* ctx);
+void ctx_release(Ctx* ctx);
 void free_loss_scratch(Ctx* ctx);
 
 // Records HIP events around a stage on stream s when the context times stages.

@@ -202,6 +202,31 @@ __device__ inline void project_view(const Body& b, const CamDev& c, int tile, Pr
   p.touched = true;
 }
 
+// Smallest fp16 not below x > 0 (bits); +inf past the largest finite value.
+__device__ inline uint32_t half_bits_up(float x) {
+  const _Float16 h = (_Float16)x;
+  uint16_t b;
+  __builtin_memcpy(&b, &h, 2);
+  if ((float)h < x) ++b;  // positive halves order like their bit patterns
+  return b;
+}
+
+// Half-widths of the axis-aligned box outside which alpha < 1/255 for certain,
+// from the stored float32 conic and opacity: the ellipse power >= -ln(255 o)
+// bounded by sqrt(c2 C / det) and sqrt(c2 A / det), widened by 1% + 0.01 px and
+// rounded up to fp16 (x in the low half, y in the high).  Negative (-1) when
+// the splat can never pass the alpha test.
+__device__ inline uint32_t alpha_box_bits(float A, float B, float C, float o) {
+  const float lim = o * 255.0f;
+  // determinant in float64: the float32 conic of an elongated splat loses digits here
+  const double det = (double)A * (double)C - (double)B * (double)B;
+  if (!(lim >= 1.0f) || !(det > 0.0)) return 0xBC00BC00u;  // fp16 -1, -1
+  const double c2 = 2.0 * ((double)logf(lim) + 1e-3);  // bound of dx^T Q dx, with margin
+  const float hw = (float)(sqrt(c2 * (double)C / det) * 1.01 + 1e-2);
+  const float hh = (float)(sqrt(c2 * (double)A / det) * 1.01 + 1e-2);
+  return half_bits_up(hw) | (half_bits_up(hh) << 16);
+}
+
 template <int DEG>
 __global__ __launch_bounds__(256) void k_preprocess_fwd(ParamsDev prm, ViewTable vt,
                                                         float4* __restrict__ splat,
@@ -259,11 +284,12 @@ __global__ __launch_bounds__(256) void k_preprocess_fwd(ParamsDev prm, ViewTable
     const double fmx = floor(p.mx), fmy = floor(p.my);
     const double cmx = fmin(fmax(fmx, -1073741824.0), 1073741824.0);
     const double cmy = fmin(fmax(fmy, -1073741824.0), 1073741824.0);
-    splat[o * 3 + 0] = make_float4((float)(p.c / p.det), (float)(-p.b / p.det),
-                                   (float)(p.a / p.det), opacity);
+    const float cA = (float)(p.c / p.det), cB = (float)(-p.b / p.det), cC = (float)(p.a / p.det);
+    splat[o * 3 + 0] = make_float4(cA, cB, cC, opacity);
     splat[o * 3 + 1] = make_float4(__int_as_float((int)cmx), __int_as_float((int)cmy),
                                    (float)(0.5 - (p.mx - cmx)), (float)(0.5 - (p.my - cmy)));
-    splat[o * 3 + 2] = make_float4(rgb[0], rgb[1], rgb[2], depth);
+    splat[o * 3 + 2] =
+        make_float4(rgb[0], rgb[1], rgb[2], __uint_as_float(alpha_box_bits(cA, cB, cC, opacity)));
   }
 }
 

@@ -205,6 +205,7 @@ gs_status gs_server_create(gs_ctx* ctx, const gs_server_opts* opts, gs_server** 
     return GS_ERR_NOMEM;
   }
   sv->ctx = ctx;
+  ctx_retain(ctx);
   sv->opts = *opts;
   sv->slots.resize(opts->n_slots);
   (void)hipSetDevice(ctx->device);
@@ -388,7 +389,9 @@ void gs_server_destroy(gs_server* sv) {
     if (s.frame != nullptr) gs_frame_release(s.frame);
     if (s.stream != nullptr) (void)hipStreamDestroy(s.stream);
   }
+  gs_ctx* ctx = sv->ctx;
   delete sv;
+  ctx_release(ctx);
 }
 
 }  // extern "C"

@@ -87,7 +87,7 @@ def test_fullsize_forward_backward_sampled(P, ctx, full):
     finT = frame.export("final_T").cpu().numpy()
     ncon = frame.export("n_contrib").cpu().numpy().view(np.uint32).astype(np.int64)
     rects = frame.export("rects").cpu().numpy().view(np.uint32).reshape(len(cams), n, 2)
-    depth = frame.export("splats").cpu().numpy().reshape(len(cams), n, 12)[:, :, 11]
+    depth = frame.export("depths").cpu().numpy().view(np.uint32).reshape(len(cams), n)
     print(f"[fullsize] K = {st['n_records']}", flush=True)
 
     rng = np.random.default_rng(2024)
@@ -106,8 +106,8 @@ def test_fullsize_forward_backward_sampled(P, ctx, full):
         assert np.array_equal(x1[~t] < x0[~t], np.ones((~t).sum(), bool)), v
         for got, want in ((x0, 0), (y0, 1), (x1, 2), (y1, 3)):
             assert np.array_equal(got[t].astype(np.int64), pr["rect"][want, t]), (v, want)
-        assert np.array_equal(depth[v][t].view(np.uint32),
-                              np.asarray(pr["depth32"], np.float32)[t].view(np.uint32)), v
+        assert np.array_equal(depth[v][t], np.asarray(pr["depth32"], np.float32)[t].view(np.uint32)), v
+        assert np.all(depth[v][~t] == 0xFFFFFFFF), v
         area = (pr["rect"][2, t] - pr["rect"][0, t] + 1) * (pr["rect"][3, t] - pr["rect"][1, t] + 1)
         k_view = int(area.sum())
         vr = ranges[tile_off:tile_off + tx * ty]

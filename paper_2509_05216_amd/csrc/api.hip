@@ -622,13 +622,16 @@ gs_status forward_stages(Ctx* ctx, Frame& f, const ParamsDev& pd, hipStream_t s,
   if (st != GS_OK) return st;
   f.sidx_sel = in_b;
   const uint32_t* sidx = (const uint32_t*)f.sidx[in_b].p;
-  // 3. record offsets and the total K
+  // 3. record offsets and the total K; the depth sort's key buffers are free now
+  // and take the rectangles in depth order (x0|y0 words, x1|y1 words)
   uint32_t* words = (uint32_t*)f.words.p;
   uint64_t* d_total = (uint64_t*)(words + kWordTotal);
+  uint32_t* srx = (uint32_t*)f.dkw[0].p;
+  uint32_t* sry = (uint32_t*)f.dkw[1].p;
   {
     StageTimer tm(ctx, ST_SCAN, s);
-    st = scan_tile_counts(ctx, f.ss, sidx, (const uint2*)f.rect.p, vn, (uint32_t*)f.offs.p,
-                          d_total, s);
+    st = scan_tile_counts(ctx, f.ss, sidx, (const uint2*)f.rect.p, vn, (uint32_t*)f.offs.p, srx,
+                          sry, d_total, s);
   }
   if (st != GS_OK) return st;
   uint32_t n_rec = 0;              // host bound on the record count (grid sizes)
@@ -661,7 +664,7 @@ gs_status forward_stages(Ctx* ctx, Frame& f, const ParamsDev& pd, hipStream_t s,
   // 4. records in depth order, then the stable sort on the tile digits
   {
     StageTimer tm(ctx, ST_EMIT, s);
-    st = launch_emit(f.vt, f, sidx, vn, overflow, s);
+    st = launch_emit(f.vt, f, sidx, srx, sry, vn, overflow, s);
   }
   if (st != GS_OK) return st;
   {

@@ -228,8 +228,12 @@ gs_status launch_init_points(const float* xyz, int64_t n, const gs_init_opts& o,
 gs_status sort_pairs_u32(Ctx* ctx, SortScratch& ss, const uint32_t* kin, const uint32_t* vin,
                          uint32_t* kA, uint32_t* vA, uint32_t* kB, uint32_t* vB, uint32_t n,
                          const uint32_t* d_n, int bits, int* result_in_b, hipStream_t s);
+// Tile counts of the depth-ordered entries, scanned into record offsets; the
+// entries' rectangles are also written in that order (srx, sry: the two halves)
+// so the emission reads them coalesced.
 gs_status scan_tile_counts(Ctx* ctx, SortScratch& ss, const uint32_t* sidx, const uint2* rect,
-                           uint32_t n, uint32_t* offs, uint64_t* d_total, hipStream_t s);
+                           uint32_t n, uint32_t* offs, uint32_t* srx, uint32_t* sry,
+                           uint64_t* d_total, hipStream_t s);
 // Scratch for sorts of up to n pairs (so that no allocation happens later, e.g. in capture).
 gs_status sort_reserve(Ctx* ctx, SortScratch& ss, uint32_t n);
 // K = min(*total, cap); *overflow |= (*total > cap).
@@ -237,8 +241,8 @@ gs_status launch_clamp_count(const uint64_t* total, uint32_t cap, uint32_t* K,
                              uint32_t* overflow, hipStream_t s);
 // Records of count (view, Gaussian) entries; overflow (optional) is set, and the
 // entry skipped, when its records would pass the record buffers' capacity.
-gs_status launch_emit(const ViewTable& vt, Frame& f, const uint32_t* sidx, uint32_t count,
-                      uint32_t* overflow, hipStream_t s);
+gs_status launch_emit(const ViewTable& vt, Frame& f, const uint32_t* sidx, const uint32_t* srx,
+                      const uint32_t* sry, uint32_t count, uint32_t* overflow, hipStream_t s);
 // Per-tile ranges of n_rec records (d_K: device count bounding n_rec, optional).
 gs_status launch_ranges(Frame& f, uint32_t n_rec, const uint32_t* d_K, hipStream_t s);
 // Tiles in descending list length (ties by tile id) for the persistent queue.

@@ -60,18 +60,6 @@ __device__ inline uint64_t block_exclusive_scan(uint64_t x, uint64_t* sh_waves, 
   return before + inc - x;
 }
 
-// Scan input: tile counts of (view, Gaussian) entries in sorted order.
-struct CountsIn {
-  const uint32_t* sidx;
-  const uint2* rect;
-  __device__ uint32_t operator()(uint32_t i) const {
-    const uint2 r = rect[sidx[i]];
-    const int x0 = (int)(r.x & 0xffffu), y0 = (int)(r.x >> 16);
-    const int x1 = (int)(r.y & 0xffffu), y1 = (int)(r.y >> 16);
-    if (x1 < x0 || y1 < y0) return 0u;
-    return (uint32_t)((x1 - x0 + 1) * (y1 - y0 + 1));
-  }
-};
 
 struct ArrayIn {
   const uint32_t* a;
@@ -150,11 +138,21 @@ __global__ __launch_bounds__(kThreads) void k_scan_down(F f, uint32_t n, const u
 }
 
 // Tile count of every (view, Gaussian) entry in depth order (one gather).
+// The one random gather of the rectangles: tile counts in depth order, and the
+// rectangles themselves in that order for the emission.
 __global__ __launch_bounds__(256) void k_counts(const uint32_t* __restrict__ sidx,
                                                 const uint2* __restrict__ rect, uint32_t n,
-                                                uint32_t* __restrict__ counts) {
+                                                uint32_t* __restrict__ counts,
+                                                uint32_t* __restrict__ srx,
+                                                uint32_t* __restrict__ sry) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) counts[i] = CountsIn{sidx, rect}(i);
+  if (i >= n) return;
+  const uint2 r = rect[sidx[i]];
+  srx[i] = r.x;
+  sry[i] = r.y;
+  const int x0 = (int)(r.x & 0xffffu), y0 = (int)(r.x >> 16);
+  const int x1 = (int)(r.y & 0xffffu), y1 = (int)(r.y >> 16);
+  counts[i] = (x1 < x0 || y1 < y0) ? 0u : (uint32_t)((x1 - x0 + 1) * (y1 - y0 + 1));
 }
 
 // ---------------------------------------------------------------- radix sort
@@ -271,7 +269,8 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(
 // ---------------------------------------------------------------- emission
 __global__ __launch_bounds__(256) void k_emit(ViewTable vt, int n_gauss,
                                               const uint32_t* __restrict__ sidx,
-                                              const uint2* __restrict__ rect,
+                                              const uint32_t* __restrict__ srx,
+                                              const uint32_t* __restrict__ sry,
                                               const uint32_t* __restrict__ offs, uint32_t count,
                                               uint32_t cap, uint32_t* __restrict__ tkey,
                                               uint32_t* __restrict__ tval,
@@ -279,7 +278,7 @@ __global__ __launch_bounds__(256) void k_emit(ViewTable vt, int n_gauss,
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= count) return;
   const uint32_t idx = sidx[i];
-  const uint2 r = rect[idx];
+  const uint2 r = make_uint2(srx[i], sry[i]);  // rect[idx], gathered in depth order by k_counts
   const int x0 = (int)(r.x & 0xffffu), y0 = (int)(r.x >> 16);
   const int x1 = (int)(r.y & 0xffffu), y1 = (int)(r.y >> 16);
   if (x1 < x0 || y1 < y0) return;
@@ -364,12 +363,14 @@ static gs_status ensure_scratch(Ctx* ctx, SortScratch& ss, uint32_t nb, size_t h
 }
 
 gs_status scan_tile_counts(Ctx* ctx, SortScratch& ss, const uint32_t* sidx, const uint2* rect,
-                           uint32_t n, uint32_t* offs, uint64_t* d_total, hipStream_t s) {
+                           uint32_t n, uint32_t* offs, uint32_t* srx, uint32_t* sry,
+                           uint64_t* d_total, hipStream_t s) {
   const uint32_t nb = nblocks_of(n);
   gs_status st = ensure_scratch(ctx, ss, nb, 0);
   if (st != GS_OK) return st;
   // gather the counts once (random rect reads), then scan them in place, coalesced
-  hipLaunchKernelGGL(k_counts, dim3((n + 255) / 256), dim3(256), 0, s, sidx, rect, n, offs);
+  hipLaunchKernelGGL(k_counts, dim3((n + 255) / 256), dim3(256), 0, s, sidx, rect, n, offs, srx,
+                     sry);
   GS_LAUNCHED("counts");
   ArrayIn f{offs};
   auto* partial = (uint64_t*)ss.partial.p;
@@ -422,14 +423,14 @@ gs_status sort_pairs_u32(Ctx* ctx, SortScratch& ss, const uint32_t* kin, const u
   return GS_OK;
 }
 
-gs_status launch_emit(const ViewTable& vt, Frame& f, const uint32_t* sidx, uint32_t count,
-                      uint32_t* overflow, hipStream_t s) {
+gs_status launch_emit(const ViewTable& vt, Frame& f, const uint32_t* sidx, const uint32_t* srx,
+                      const uint32_t* sry, uint32_t count, uint32_t* overflow, hipStream_t s) {
   if (count == 0) return GS_OK;
   const size_t cap_bytes = f.tkey[0].cap < f.tval[0].cap ? f.tkey[0].cap : f.tval[0].cap;
   const uint32_t cap = (uint32_t)(cap_bytes / sizeof(uint32_t));
-  hipLaunchKernelGGL(k_emit, dim3((count + 255) / 256), dim3(256), 0, s, vt, (int)f.n, sidx,
-                     (const uint2*)f.rect.p, (const uint32_t*)f.offs.p, count, cap,
-                     (uint32_t*)f.tkey[0].p, (uint32_t*)f.tval[0].p, overflow);
+  hipLaunchKernelGGL(k_emit, dim3((count + 255) / 256), dim3(256), 0, s, vt, (int)f.n, sidx, srx,
+                     sry, (const uint32_t*)f.offs.p, count, cap, (uint32_t*)f.tkey[0].p,
+                     (uint32_t*)f.tval[0].p, overflow);
   GS_LAUNCHED("emit");
   return GS_OK;
 }

@@ -126,32 +126,36 @@ __device__ inline void load_body(const ParamsDev& p, int i, Body& b) {
                          M[r * 3 + 2] * M[c * 3 + 2];
 }
 
-// Per-view projected state.
-struct Proj {
-  double t[3];
-  double xz, yz, u, v, limx, limy;
-  double J00, J02, J11, J12;
-  double T0[3], T1[3];
-  double S0[3], S1[3];  // Sigma3 T0, Sigma3 T1
-  double a, b, c, det;
-  double mx, my;
+// Per-view projected state (R = double for the forward, whose binning
+// decisions must be those of any float64 evaluation; float for the backward).
+template <typename R>
+struct ProjT {
+  R t[3];
+  R xz, yz, u, v, limx, limy;
+  R J00, J02, J11, J12;
+  R T0[3], T1[3];
+  R S0[3], S1[3];  // Sigma3 T0, Sigma3 T1
+  R a, b, c, det;
+  R mx, my;
   int radius;
   int x0, y0, x1, y1;  // tile rectangle (inclusive); empty if !touched
   bool visible, touched;
 };
+using Proj = ProjT<double>;
 
 // Camera-space mean, Jacobian and 2-D covariance (with the low-pass) of one view.
-__device__ inline void view_cov(const double* mu, const double* Sig, const CamDev& c, Proj& p) {
-  const float* R = c.R;
+template <typename R>
+__device__ inline void view_cov(const R* mu, const R* Sig, const CamDev& c, ProjT<R>& p) {
+  const float* Rc = c.R;
   for (int r = 0; r < 3; ++r)
-    p.t[r] = (double)R[r * 3 + 0] * mu[0] + (double)R[r * 3 + 1] * mu[1] +
-             (double)R[r * 3 + 2] * mu[2] + (double)c.t[r];
+    p.t[r] = (R)Rc[r * 3 + 0] * mu[0] + (R)Rc[r * 3 + 1] * mu[1] + (R)Rc[r * 3 + 2] * mu[2] +
+             (R)c.t[r];
   p.touched = false;
-  p.visible = p.t[2] > (double)c.znear;
-  const double tz = p.visible ? p.t[2] : 1.0;
-  const double fx = c.fx, fy = c.fy;
-  p.limx = kGuard * (0.5 * (double)c.W / fx);
-  p.limy = kGuard * (0.5 * (double)c.H / fy);
+  p.visible = p.t[2] > (R)c.znear;
+  const R tz = p.visible ? p.t[2] : R(1);
+  const R fx = (R)c.fx, fy = (R)c.fy;
+  p.limx = R(kGuard) * (R(0.5) * (R)c.W / fx);
+  p.limy = R(kGuard) * (R(0.5) * (R)c.H / fy);
   p.xz = p.t[0] / tz;
   p.yz = p.t[1] / tz;
   p.u = fmin(fmax(p.xz, -p.limx), p.limx);
@@ -161,21 +165,21 @@ __device__ inline void view_cov(const double* mu, const double* Sig, const CamDe
   p.J11 = fy / tz;
   p.J12 = -fy * p.v / tz;
   for (int j = 0; j < 3; ++j) {
-    p.T0[j] = p.J00 * (double)R[0 * 3 + j] + p.J02 * (double)R[2 * 3 + j];
-    p.T1[j] = p.J11 * (double)R[1 * 3 + j] + p.J12 * (double)R[2 * 3 + j];
+    p.T0[j] = p.J00 * (R)Rc[0 * 3 + j] + p.J02 * (R)Rc[2 * 3 + j];
+    p.T1[j] = p.J11 * (R)Rc[1 * 3 + j] + p.J12 * (R)Rc[2 * 3 + j];
   }
-  double* S0 = p.S0;
-  double* S1 = p.S1;
+  R* S0 = p.S0;
+  R* S1 = p.S1;
   for (int r = 0; r < 3; ++r) {
     S0[r] = Sig[r * 3 + 0] * p.T0[0] + Sig[r * 3 + 1] * p.T0[1] + Sig[r * 3 + 2] * p.T0[2];
     S1[r] = Sig[r * 3 + 0] * p.T1[0] + Sig[r * 3 + 1] * p.T1[1] + Sig[r * 3 + 2] * p.T1[2];
   }
-  p.a = p.T0[0] * S0[0] + p.T0[1] * S0[1] + p.T0[2] * S0[2] + kLowpass;
+  p.a = p.T0[0] * S0[0] + p.T0[1] * S0[1] + p.T0[2] * S0[2] + R(kLowpass);
   p.b = p.T0[0] * S1[0] + p.T0[1] * S1[1] + p.T0[2] * S1[2];
-  p.c = p.T1[0] * S1[0] + p.T1[1] * S1[1] + p.T1[2] * S1[2] + kLowpass;
+  p.c = p.T1[0] * S1[0] + p.T1[1] * S1[1] + p.T1[2] * S1[2] + R(kLowpass);
   p.det = p.a * p.c - p.b * p.b;
-  p.mx = fx * p.xz + (double)c.cx;
-  p.my = fy * p.yz + (double)c.cy;
+  p.mx = fx * p.xz + (R)c.cx;
+  p.my = fy * p.yz + (R)c.cy;
 }
 
 // view_cov plus the radius and the tile rectangle (the binning decisions).
@@ -294,32 +298,142 @@ __global__ __launch_bounds__(256) void k_preprocess_fwd(ParamsDev prm, ViewTable
 }
 
 // Chain rule from the screen-space accumulators (9 per view) to the parameters.
-//
-// Three phases keep few values live at a time:
-//  1. geometry, float64, per view: conic and mean2D gradients -> dL/dt (camera
-//     space) -> dL/dmean, and dL/dSigma3 summed over the views (dL/dSigma3 is
-//     all that the scale and rotation gradients need, so their chain runs once);
-//  2. SH colour, float32, per view: dL/d(SH coefficients) and the gradient of
-//     the view direction with respect to the mean; the accumulators are
-//     cleared for the next pass here;
-//  3. scale and rotation from the summed dL/dSigma3.
-template <int DEG>
-__global__ __launch_bounds__(256) void k_preprocess_bwd(ParamsDev prm, ViewTable vt,
-                                                        float* __restrict__ acc,
-                                                        const uint2* __restrict__ rect,
-                                                        const uint8_t* __restrict__ clampm,
-                                                        GradsDev gout) {
+// No bit-exact decision is taken here, so the geometry runs in float32.  For
+// several views it is split in two kernels so that each keeps few values live:
+//  * geometry: per view, conic and mean2D gradients -> dL/dt (camera space) ->
+//    dL/dmean, and dL/dSigma3 summed over the views; then the scale and
+//    rotation gradients once from that sum, and the opacity gradient;
+//  * colour: per view, dL/d(SH coefficients) and the gradient of the view
+//    direction with respect to the mean (added to the geometry kernel's mean
+//    gradient); it also clears the accumulators for the next pass.
+// A single view takes one fused kernel (k_preprocess_bwd_one).
+
+// One view's geometric terms: the conic, mean2D and opacity sums (a0, a1.xy of
+// the accumulator) -> dL/dmean (camera-space chain) and dL/dSigma3 (symmetrised,
+// entries 00 01 02 11 12 22), added to g_mu and Gs; opacity sum added to g_op.
+__device__ inline void geom_view(const float* mu, const float* Sig, const CamDev& c, float4 a0,
+                                 float4 a1, float* g_mu, float* Gs, float& g_op) {
+  ProjT<float> p;
+  view_cov(mu, Sig, c, p);
+  const float gmx = a0.x, gmy = a0.y, gA = a0.z, gB = a0.w, gC = a1.x;
+  g_op += a1.y;
+  // conic (A, B, C) = (c, -b, a) / det
+  const float iD = 1.f / p.det;
+  const float gD = -(gA * p.c - gB * p.b + gC * p.a) * iD * iD;
+  const float ga = gC * iD + gD * p.c;
+  const float gb = -gB * iD - 2.f * gD * p.b;
+  const float gc = gA * iD + gD * p.a;
+  // Sigma2 = T Sigma3 T^T: dL/dT rows, and G + G^T with
+  // G = ga T0 T0^T + gb T0 T1^T + gc T1 T1^T
+  float gT0[3], gT1[3];
+  for (int r = 0; r < 3; ++r) {
+    gT0[r] = 2.f * ga * p.S0[r] + gb * p.S1[r];
+    gT1[r] = gb * p.S0[r] + 2.f * gc * p.S1[r];
+  }
+  {
+    int k = 0;
+    for (int r = 0; r < 3; ++r)
+      for (int q = r; q < 3; ++q, ++k) {
+        const float g1 = ga * p.T0[r] * p.T0[q] + gb * p.T0[r] * p.T1[q] + gc * p.T1[r] * p.T1[q];
+        const float g2 = ga * p.T0[q] * p.T0[r] + gb * p.T0[q] * p.T1[r] + gc * p.T1[q] * p.T1[r];
+        Gs[k] += g1 + g2;
+      }
+  }
+  // T = J R  ->  dJ = dT R^T (only the four non-zero Jacobian entries matter)
+  const float* R = c.R;
+  float gJ00 = 0.f, gJ02 = 0.f, gJ11 = 0.f, gJ12 = 0.f;
+  for (int k = 0; k < 3; ++k) {
+    gJ00 += gT0[k] * R[0 * 3 + k];
+    gJ02 += gT0[k] * R[2 * 3 + k];
+    gJ11 += gT1[k] * R[1 * 3 + k];
+    gJ12 += gT1[k] * R[2 * 3 + k];
+  }
+  const float tx = p.t[0], ty = p.t[1], tz = p.t[2];
+  const float fx = c.fx, fy = c.fy;
+  const float itz = 1.f / tz, itz2 = itz * itz;
+  float gt[3] = {0.f, 0.f, 0.f};
+  gt[2] += gJ00 * (-fx * itz2) + gJ11 * (-fy * itz2) + gJ02 * (fx * p.u * itz2) +
+           gJ12 * (fy * p.v * itz2);
+  const float gu = gJ02 * (-fx * itz);
+  const float gv = gJ12 * (-fy * itz);
+  if (p.xz >= -p.limx && p.xz <= p.limx) {
+    gt[0] += gu * itz;
+    gt[2] += -gu * tx * itz2;
+  }
+  if (p.yz >= -p.limy && p.yz <= p.limy) {
+    gt[1] += gv * itz;
+    gt[2] += -gv * ty * itz2;
+  }
+  // mean2D
+  gt[0] += gmx * fx * itz;
+  gt[1] += gmy * fy * itz;
+  gt[2] += -(gmx * fx * tx + gmy * fy * ty) * itz2;
+  for (int k = 0; k < 3; ++k)
+    g_mu[k] += R[0 * 3 + k] * gt[0] + R[1 * 3 + k] * gt[1] + R[2 * 3 + k] * gt[2];
+}
+
+// Scale and rotation gradients from the summed dL/dSigma3, and the opacity
+// logit's from the summed opacity gradient (float64 body of Gaussian i).
+__device__ inline void geom_finish(const ParamsDev& prm, int i, const float* Gs, float g_op,
+                                   float* g_ls, float* g_q, float& g_logit) {
+  Body b;
+  load_body(prm, i, b);
+  const double G[9] = {Gs[0], Gs[1], Gs[2], Gs[1], Gs[3], Gs[4], Gs[2], Gs[4], Gs[5]};
+  // Sigma3 = M M^T, M = Rq diag(s)
+  double M[9];
+  for (int r = 0; r < 3; ++r)
+    for (int q = 0; q < 3; ++q) M[r * 3 + q] = b.Rq[r * 3 + q] * b.s[q];
+  double gM[9];
+  for (int r = 0; r < 3; ++r)
+    for (int q = 0; q < 3; ++q)
+      gM[r * 3 + q] = G[r * 3 + 0] * M[0 * 3 + q] + G[r * 3 + 1] * M[1 * 3 + q] +
+                      G[r * 3 + 2] * M[2 * 3 + q];
+  double gR[9];
+  for (int r = 0; r < 3; ++r)
+    for (int q = 0; q < 3; ++q) gR[r * 3 + q] = gM[r * 3 + q] * b.s[q];
+  for (int q = 0; q < 3; ++q) {
+    const double gsq = gM[0 * 3 + q] * b.Rq[0 * 3 + q] + gM[1 * 3 + q] * b.Rq[1 * 3 + q] +
+                       gM[2 * 3 + q] * b.Rq[2 * 3 + q];
+    g_ls[q] = (float)(gsq * b.s[q]);
+  }
+  // rotation of the unit quaternion, entry by entry
+  const double w = b.qn[0], x = b.qn[1], y = b.qn[2], z = b.qn[3];
+  const double* g = gR;
+  const double gw = 2 * (-z * g[1] + y * g[2] + z * g[3] - x * g[5] - y * g[6] + x * g[7]);
+  const double gx = 2 * (y * g[1] + z * g[2] + y * g[3] - 2 * x * g[4] - w * g[5] + z * g[6] +
+                         w * g[7] - 2 * x * g[8]);
+  const double gy = 2 * (-2 * y * g[0] + x * g[1] + w * g[2] + x * g[3] + z * g[5] - w * g[6] +
+                         z * g[7] - 2 * y * g[8]);
+  const double gz = 2 * (-2 * z * g[0] - w * g[1] + x * g[2] + w * g[3] - 2 * z * g[4] +
+                         y * g[5] + x * g[6] + y * g[7]);
+  const double dot = w * gw + x * gx + y * gy + z * gz;
+  g_q[0] = (float)((gw - w * dot) / b.qnorm);
+  g_q[1] = (float)((gx - x * dot) / b.qnorm);
+  g_q[2] = (float)((gy - y * dot) / b.qnorm);
+  g_q[3] = (float)((gz - z * dot) / b.qnorm);
+  const double op = 1.0 / (1.0 + exp(-(double)prm.logits[i]));
+  g_logit = (float)(g_op * op * (1.0 - op));
+}
+
+// Mean, Sigma3 (float32) of Gaussian i.
+__device__ inline void geom_body(const ParamsDev& prm, int i, float* mu, float* Sig) {
+  Body b;
+  load_body(prm, i, b);
+  for (int k = 0; k < 3; ++k) mu[k] = (float)b.mu[k];
+  for (int k = 0; k < 9; ++k) Sig[k] = (float)b.Sig[k];
+}
+
+__global__ __launch_bounds__(256) void k_preprocess_bwd_geom(ParamsDev prm, ViewTable vt,
+                                                             const float* __restrict__ acc,
+                                                             const uint2* __restrict__ rect,
+                                                             GradsDev gout) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int n = prm.n;
   if (i >= n) return;
-  constexpr int deg = DEG;
-  constexpr int nb = (DEG + 1) * (DEG + 1);
-
-  // ---- 1. geometry
-  double mu[3], Sig[9];
-  bool loaded = false, any = false;
-  double g_mu[3] = {0, 0, 0}, g_op = 0;
-  double Gs[6] = {0, 0, 0, 0, 0, 0};  // dL/dSigma3 (symmetrised): 00 01 02 11 12 22
+  float mu[3], Sig[9];
+  bool loaded = false;
+  float g_mu[3] = {0.f, 0.f, 0.f}, g_op = 0.f;
+  float Gs[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   for (int v = 0; v < vt.n; ++v) {
     const size_t o = (size_t)v * n + i;
     const uint2 rc = rect[o];
@@ -329,191 +443,260 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(ParamsDev prm, ViewTable
     if (a0.x == 0.f && a0.y == 0.f && a0.z == 0.f && a0.w == 0.f && a1.x == 0.f && a1.y == 0.f)
       continue;
     if (!loaded) {
-      Body b;
-      load_body(prm, i, b);
-      for (int k = 0; k < 3; ++k) mu[k] = b.mu[k];
-      for (int k = 0; k < 9; ++k) Sig[k] = b.Sig[k];
+      geom_body(prm, i, mu, Sig);
       loaded = true;
     }
-    const CamDev& c = vt.v[v];
-    Proj p;
-    view_cov(mu, Sig, c, p);
-    const double gmx = a0.x, gmy = a0.y, gA = a0.z, gB = a0.w, gC = a1.x;
-    g_op += a1.y;
-    // conic (A, B, C) = (c, -b, a) / det
-    const double D = p.det;
-    const double gD = -(gA * p.c - gB * p.b + gC * p.a) / (D * D);
-    const double ga = gC / D + gD * p.c;
-    const double gb = -gB / D - 2.0 * gD * p.b;
-    const double gc = gA / D + gD * p.a;
-    // Sigma2 = T Sigma3 T^T: dL/dT rows, and G + G^T with
-    // G = ga T0 T0^T + gb T0 T1^T + gc T1 T1^T
-    double gT0[3], gT1[3];
-    for (int r = 0; r < 3; ++r) {
-      gT0[r] = 2.0 * ga * p.S0[r] + gb * p.S1[r];
-      gT1[r] = gb * p.S0[r] + 2.0 * gc * p.S1[r];
-    }
-    {
-      int k = 0;
-      for (int r = 0; r < 3; ++r)
-        for (int q = r; q < 3; ++q, ++k) {
-          const double g1 = ga * p.T0[r] * p.T0[q] + gb * p.T0[r] * p.T1[q] + gc * p.T1[r] * p.T1[q];
-          const double g2 = ga * p.T0[q] * p.T0[r] + gb * p.T0[q] * p.T1[r] + gc * p.T1[q] * p.T1[r];
-          Gs[k] += g1 + g2;
-        }
-    }
-    // T = J R  ->  dJ = dT R^T (only the four non-zero Jacobian entries matter)
-    const float* R = c.R;
-    double gJ00 = 0, gJ02 = 0, gJ11 = 0, gJ12 = 0;
-    for (int k = 0; k < 3; ++k) {
-      gJ00 += gT0[k] * (double)R[0 * 3 + k];
-      gJ02 += gT0[k] * (double)R[2 * 3 + k];
-      gJ11 += gT1[k] * (double)R[1 * 3 + k];
-      gJ12 += gT1[k] * (double)R[2 * 3 + k];
-    }
-    const double tx = p.t[0], ty = p.t[1], tz = p.t[2];
-    const double fx = c.fx, fy = c.fy;
-    double gt[3] = {0, 0, 0};
-    gt[2] += gJ00 * (-fx / (tz * tz)) + gJ11 * (-fy / (tz * tz)) + gJ02 * (fx * p.u / (tz * tz)) +
-             gJ12 * (fy * p.v / (tz * tz));
-    const double gu = gJ02 * (-fx / tz);
-    const double gv = gJ12 * (-fy / tz);
-    if (p.xz >= -p.limx && p.xz <= p.limx) {
-      gt[0] += gu / tz;
-      gt[2] += -gu * tx / (tz * tz);
-    }
-    if (p.yz >= -p.limy && p.yz <= p.limy) {
-      gt[1] += gv / tz;
-      gt[2] += -gv * ty / (tz * tz);
-    }
-    // mean2D
-    gt[0] += gmx * fx / tz;
-    gt[1] += gmy * fy / tz;
-    gt[2] += -(gmx * fx * tx + gmy * fy * ty) / (tz * tz);
-    for (int k = 0; k < 3; ++k)
-      g_mu[k] += (double)R[0 * 3 + k] * gt[0] + (double)R[1 * 3 + k] * gt[1] +
-                 (double)R[2 * 3 + k] * gt[2];
+    geom_view(mu, Sig, vt.v[v], a0, a1, g_mu, Gs, g_op);
   }
-
-  // ---- 2. SH colour (float32); clears the accumulators
-  float g_sh[nb * 3];
-#pragma unroll
-  for (int j = 0; j < nb * 3; ++j) g_sh[j] = 0.f;
-  float gmf[3] = {0.f, 0.f, 0.f};
-  float mf[3] = {0.f, 0.f, 0.f};
-  bool mf_loaded = false;
-  for (int v = 0; v < vt.n; ++v) {
-    const size_t o = (size_t)v * n + i;
-    const uint2 rc = rect[o];
-    if ((rc.y & 0xffffu) < (rc.x & 0xffffu)) continue;
-    float4* a = reinterpret_cast<float4*>(acc + o * kAccStride);
-    const float4 a0 = a[0], a1 = a[1], a2 = a[2];
-    const bool geo = a0.x != 0.f || a0.y != 0.f || a0.z != 0.f || a0.w != 0.f || a1.x != 0.f ||
-                     a1.y != 0.f;
-    const bool col = a1.z != 0.f || a1.w != 0.f || a2.x != 0.f;
-    if (!geo && !col) continue;
-    // leave the accumulator cleared for the next backward pass
-    const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
-    a[0] = zero4;
-    a[1] = zero4;
-    a[2] = zero4;
-    any = true;
-    if (!col) continue;
-    const uint32_t mask = clampm[o];
-    const float grgb[3] = {(mask & 1u) ? 0.f : a1.z, (mask & 2u) ? 0.f : a1.w,
-                           (mask & 4u) ? 0.f : a2.x};
-    if (!mf_loaded) {
-      for (int k = 0; k < 3; ++k) mf[k] = (float)(double)prm.means[k * n + i];
-      mf_loaded = true;
-    }
-    const CamDev& c = vt.v[v];
-    float dx = mf[0] - c.campos[0];
-    float dy = mf[1] - c.campos[1];
-    float dz = mf[2] - c.campos[2];
-    const float len = sqrtf(dx * dx + dy * dy + dz * dz);
-    const float inv = 1.0f / len;
-    dx *= inv;
-    dy *= inv;
-    dz *= inv;
-    float Y[16];
-    sh_basis(dx, dy, dz, deg, Y);
-    float w[16];
-#pragma unroll
-    for (int j = 0; j < nb; ++j) {
-      float s = 0.f;
-#pragma unroll
-      for (int ch = 0; ch < 3; ++ch) {
-        g_sh[j * 3 + ch] += Y[j] * grgb[ch];
-        s += prm.sh[(size_t)(j * 3 + ch) * n + i] * grgb[ch];
-      }
-      w[j] = s;
-    }
-    float gx = 0.f, gy = 0.f, gz = 0.f;
-    sh_basis_grad_dot(dx, dy, dz, deg, w, gx, gy, gz);
-    const float dot = gx * dx + gy * dy + gz * dz;
-    gmf[0] += (gx - dx * dot) * inv;
-    gmf[1] += (gy - dy * dot) * inv;
-    gmf[2] += (gz - dz * dot) * inv;
-  }
-  for (int k = 0; k < 3; ++k) g_mu[k] += (double)gmf[k];
-
-  // ---- 3. scale and rotation from dL/dSigma3; opacity
-  double g_ls[3] = {0, 0, 0}, g_q[4] = {0, 0, 0, 0}, g_logit = 0;
-  if (loaded) {
-    Body b;
-    load_body(prm, i, b);
-    const double G[9] = {Gs[0], Gs[1], Gs[2], Gs[1], Gs[3], Gs[4], Gs[2], Gs[4], Gs[5]};
-    // Sigma3 = M M^T, M = Rq diag(s)
-    double M[9];
-    for (int r = 0; r < 3; ++r)
-      for (int q = 0; q < 3; ++q) M[r * 3 + q] = b.Rq[r * 3 + q] * b.s[q];
-    double gM[9];
-    for (int r = 0; r < 3; ++r)
-      for (int q = 0; q < 3; ++q)
-        gM[r * 3 + q] = G[r * 3 + 0] * M[0 * 3 + q] + G[r * 3 + 1] * M[1 * 3 + q] +
-                        G[r * 3 + 2] * M[2 * 3 + q];
-    double gR[9];
-    for (int r = 0; r < 3; ++r)
-      for (int q = 0; q < 3; ++q) gR[r * 3 + q] = gM[r * 3 + q] * b.s[q];
-    for (int q = 0; q < 3; ++q) {
-      const double gsq = gM[0 * 3 + q] * b.Rq[0 * 3 + q] + gM[1 * 3 + q] * b.Rq[1 * 3 + q] +
-                         gM[2 * 3 + q] * b.Rq[2 * 3 + q];
-      g_ls[q] = gsq * b.s[q];
-    }
-    // rotation of the unit quaternion, entry by entry
-    const double w = b.qn[0], x = b.qn[1], y = b.qn[2], z = b.qn[3];
-    const double* g = gR;
-    const double gw = 2 * (-z * g[1] + y * g[2] + z * g[3] - x * g[5] - y * g[6] + x * g[7]);
-    const double gx = 2 * (y * g[1] + z * g[2] + y * g[3] - 2 * x * g[4] - w * g[5] + z * g[6] +
-                           w * g[7] - 2 * x * g[8]);
-    const double gy = 2 * (-2 * y * g[0] + x * g[1] + w * g[2] + x * g[3] + z * g[5] - w * g[6] +
-                           z * g[7] - 2 * y * g[8]);
-    const double gz = 2 * (-2 * z * g[0] - w * g[1] + x * g[2] + w * g[3] - 2 * z * g[4] +
-                           y * g[5] + x * g[6] + y * g[7]);
-    const double dot = w * gw + x * gx + y * gy + z * gz;
-    g_q[0] = (gw - w * dot) / b.qnorm;
-    g_q[1] = (gx - x * dot) / b.qnorm;
-    g_q[2] = (gy - y * dot) / b.qnorm;
-    g_q[3] = (gz - z * dot) / b.qnorm;
-    const double op = 1.0 / (1.0 + exp(-(double)prm.logits[i]));
-    g_logit = g_op * op * (1.0 - op);
-  }
+  float g_ls[3] = {0.f, 0.f, 0.f}, g_q[4] = {0.f, 0.f, 0.f, 0.f}, g_logit = 0.f;
+  if (loaded) geom_finish(prm, i, Gs, g_op, g_ls, g_q, g_logit);
   // write (or add) the gradients; untouched Gaussians get zeros
   const bool add = gout.accumulate != 0;
-  auto put = [&](float* dst, double val) {
+  auto put = [&](float* dst, float val) {
     if (add) {
-      if (any) *dst += (float)val;
+      if (loaded) *dst += val;
     } else {
-      *dst = (float)val;
+      *dst = val;
     }
   };
   for (int k = 0; k < 3; ++k) put(gout.means + (size_t)k * n + i, g_mu[k]);
   for (int k = 0; k < 3; ++k) put(gout.log_scales + (size_t)k * n + i, g_ls[k]);
   for (int k = 0; k < 4; ++k) put(gout.quats + (size_t)k * n + i, g_q[k]);
   put(gout.logits + i, g_logit);
-#pragma unroll
-  for (int j = 0; j < nb * 3; ++j) put(gout.sh + (size_t)j * n + i, (double)g_sh[j]);
 }
+
+// The whole chain for a single-view frame in one pass: each SH coefficient's
+// gradient (Y_j times the colour gradient) is stored as soon as it is formed.
+template <int DEG>
+__global__ __launch_bounds__(256) void k_preprocess_bwd_one(ParamsDev prm, ViewTable vt,
+                                                            float* __restrict__ acc,
+                                                            const uint2* __restrict__ rect,
+                                                            const uint8_t* __restrict__ clampm,
+                                                            GradsDev gout) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int n = prm.n;
+  if (i >= n) return;
+  constexpr int deg = DEG;
+  constexpr int nb = (DEG + 1) * (DEG + 1);
+  const bool add = gout.accumulate != 0;
+  float g_mu[3] = {0.f, 0.f, 0.f}, g_op = 0.f;
+  float Gs[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  bool geo = false, col = false;
+  float gr[3] = {0.f, 0.f, 0.f};
+  const uint2 rc = rect[i];
+  if ((rc.y & 0xffffu) >= (rc.x & 0xffffu)) {
+    float4* a = reinterpret_cast<float4*>(acc + (size_t)i * kAccStride);
+    const float4 a0 = a[0], a1 = a[1], a2 = a[2];
+    geo = a0.x != 0.f || a0.y != 0.f || a0.z != 0.f || a0.w != 0.f || a1.x != 0.f || a1.y != 0.f;
+    col = a1.z != 0.f || a1.w != 0.f || a2.x != 0.f;
+    if (geo || col) {
+      const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
+      a[0] = zero4;
+      a[1] = zero4;
+      a[2] = zero4;
+    }
+    if (geo) {
+      float mu[3], Sig[9];
+      geom_body(prm, i, mu, Sig);
+      geom_view(mu, Sig, vt.v[0], a0, a1, g_mu, Gs, g_op);
+    }
+    if (col) {
+      const uint32_t mask = clampm[i];
+      gr[0] = (mask & 1u) ? 0.f : a1.z;
+      gr[1] = (mask & 2u) ? 0.f : a1.w;
+      gr[2] = (mask & 4u) ? 0.f : a2.x;
+    }
+  }
+  // colour: dL/dsh[j][c] = Y_j gr[c]; direction term into the mean gradient
+  if (col) {
+    const CamDev& cam = vt.v[0];
+    float dx = prm.means[i] - cam.campos[0];
+    float dy = prm.means[n + i] - cam.campos[1];
+    float dz = prm.means[2 * n + i] - cam.campos[2];
+    const float inv = 1.0f / sqrtf(dx * dx + dy * dy + dz * dz);
+    dx *= inv;
+    dy *= inv;
+    dz *= inv;
+    // every coefficient is read before the first gradient store (the compiler
+    // cannot move the reads above stores to another array it cannot prove apart)
+    float w[16];
+#pragma unroll
+    for (int j = 0; j < nb; ++j) {
+      float s = 0.f;
+#pragma unroll
+      for (int ch = 0; ch < 3; ++ch) s += prm.sh[(size_t)(j * 3 + ch) * n + i] * gr[ch];
+      w[j] = s;
+    }
+    float Y[16];
+    sh_basis(dx, dy, dz, deg, Y);
+#pragma unroll
+    for (int j = 0; j < nb; ++j)
+#pragma unroll
+      for (int ch = 0; ch < 3; ++ch) {
+        float* dst = gout.sh + (size_t)(j * 3 + ch) * n + i;
+        const float v = Y[j] * gr[ch];
+        if (add)
+          *dst += v;
+        else
+          *dst = v;
+      }
+    float gx = 0.f, gy = 0.f, gz = 0.f;
+    sh_basis_grad_dot(dx, dy, dz, deg, w, gx, gy, gz);
+    const float dot = gx * dx + gy * dy + gz * dz;
+    g_mu[0] += (gx - dx * dot) * inv;
+    g_mu[1] += (gy - dy * dot) * inv;
+    g_mu[2] += (gz - dz * dot) * inv;
+  } else if (!add) {
+    for (int j = 0; j < nb * 3; ++j) gout.sh[(size_t)j * n + i] = 0.f;
+  }
+  float g_ls[3] = {0.f, 0.f, 0.f}, g_q[4] = {0.f, 0.f, 0.f, 0.f}, g_logit = 0.f;
+  if (geo) geom_finish(prm, i, Gs, g_op, g_ls, g_q, g_logit);
+  const bool any = geo || col;
+  auto put = [&](float* dst, float val) {
+    if (add) {
+      if (any) *dst += val;
+    } else {
+      *dst = val;
+    }
+  };
+  for (int k = 0; k < 3; ++k) put(gout.means + (size_t)k * n + i, g_mu[k]);
+  for (int k = 0; k < 3; ++k) put(gout.log_scales + (size_t)k * n + i, g_ls[k]);
+  for (int k = 0; k < 4; ++k) put(gout.quats + (size_t)k * n + i, g_q[k]);
+  put(gout.logits + i, g_logit);
+}
+
+// Colour part; runs after k_preprocess_bwd_geom (it adds to the mean gradient
+// that kernel wrote) and clears every accumulator it finds non-zero.  Views are
+// taken kShViews (4) at a time, and within a chunk the colour channel is
+// outermost:
+// per channel only that channel's coefficients and gradient sums are live,
+// while each view keeps its direction, colour gradient and direction gradient.
+// The direction gradient of channel c is sum_j sh[j][c] grad Y_j, scaled by the
+// view's colour gradient in c.
+template <int DEG, int kShViews>
+__global__ __launch_bounds__(256) void k_preprocess_bwd_sh(ParamsDev prm, ViewTable vt,
+                                                           float* __restrict__ acc,
+                                                           const uint2* __restrict__ rect,
+                                                           const uint8_t* __restrict__ clampm,
+                                                           GradsDev gout) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int n = prm.n;
+  if (i >= n) return;
+  constexpr int deg = DEG;
+  constexpr int nb = (DEG + 1) * (DEG + 1);
+  const bool add = gout.accumulate != 0;
+  float gmf[3] = {0.f, 0.f, 0.f};
+  float mf[3] = {0.f, 0.f, 0.f};
+  bool mf_loaded = false, wrote = false;
+  for (int v0 = 0; v0 < vt.n; v0 += kShViews) {
+    float d[kShViews][3], inv[kShViews], gr[kShViews][3], gd[kShViews][3];
+    bool act = false;
+    bool live[kShViews];  // some lane of the wave has a colour gradient in this view
+#pragma unroll
+    for (int c = 0; c < kShViews; ++c) {
+      d[c][0] = d[c][1] = d[c][2] = 0.f;
+      gr[c][0] = gr[c][1] = gr[c][2] = 0.f;
+      gd[c][0] = gd[c][1] = gd[c][2] = 0.f;
+      inv[c] = 0.f;
+      const int v = v0 + c;
+      if (v < vt.n) {
+        const size_t o = (size_t)v * n + i;
+        const uint2 rc = rect[o];
+        if ((rc.y & 0xffffu) >= (rc.x & 0xffffu)) {  // touched in this view
+          float4* a = reinterpret_cast<float4*>(acc + o * kAccStride);
+          const float4 a0 = a[0], a1 = a[1], a2 = a[2];
+          const bool geo = a0.x != 0.f || a0.y != 0.f || a0.z != 0.f || a0.w != 0.f ||
+                           a1.x != 0.f || a1.y != 0.f;
+          const bool col = a1.z != 0.f || a1.w != 0.f || a2.x != 0.f;
+          if (geo || col) {
+            // leave the accumulator cleared for the next backward pass
+            const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
+            a[0] = zero4;
+            a[1] = zero4;
+            a[2] = zero4;
+          }
+          if (col) {
+            const uint32_t mask = clampm[o];
+            gr[c][0] = (mask & 1u) ? 0.f : a1.z;
+            gr[c][1] = (mask & 2u) ? 0.f : a1.w;
+            gr[c][2] = (mask & 4u) ? 0.f : a2.x;
+            if (!mf_loaded) {
+              for (int k = 0; k < 3; ++k) mf[k] = prm.means[k * n + i];
+              mf_loaded = true;
+            }
+            const CamDev& cam = vt.v[v];
+            const float dx = mf[0] - cam.campos[0], dy = mf[1] - cam.campos[1],
+                        dz = mf[2] - cam.campos[2];
+            inv[c] = 1.0f / sqrtf(dx * dx + dy * dy + dz * dz);
+            d[c][0] = dx * inv[c];
+            d[c][1] = dy * inv[c];
+            d[c][2] = dz * inv[c];
+            act = true;
+          }
+        }
+      }
+      live[c] = __builtin_amdgcn_ballot_w64(gr[c][0] != 0.f || gr[c][1] != 0.f ||
+                                            gr[c][2] != 0.f) != 0;
+    }
+    if (!act) continue;
+    // views without colour gradient have gr = 0 and contribute nothing
+    // coefficients of channel ch + 1 are loaded while channel ch is processed
+    float shn[16];
+#pragma unroll
+    for (int j = 0; j < nb; ++j) shn[j] = prm.sh[(size_t)(j * 3) * n + i];
+#pragma unroll 1
+    for (int ch = 0; ch < 3; ++ch) {
+      float shc[16], gsh[16];
+#pragma unroll
+      for (int j = 0; j < nb; ++j) {
+        shc[j] = shn[j];
+        gsh[j] = 0.f;
+      }
+      if (ch < 2) {
+#pragma unroll
+        for (int j = 0; j < nb; ++j) shn[j] = prm.sh[(size_t)(j * 3 + ch + 1) * n + i];
+      }
+#pragma unroll
+      for (int c = 0; c < kShViews; ++c) {
+        if (!live[c]) continue;  // wave-uniform: no lane has work in this view
+        // the basis depends on the view only; the empty asm keeps the compiler from
+        // hoisting all views' basis terms out of the channel loop (register bound)
+        float x = d[c][0], y = d[c][1], z = d[c][2];
+        asm volatile("" : "+v"(x), "+v"(y), "+v"(z));
+        float Y[16];
+        sh_basis(x, y, z, deg, Y);
+        const float g = gr[c][ch];
+#pragma unroll
+        for (int j = 0; j < nb; ++j) gsh[j] += Y[j] * g;
+        float gx = 0.f, gy = 0.f, gz = 0.f;
+        sh_basis_grad_dot(x, y, z, deg, shc, gx, gy, gz);
+        gd[c][0] += g * gx;
+        gd[c][1] += g * gy;
+        gd[c][2] += g * gz;
+      }
+#pragma unroll
+      for (int j = 0; j < nb; ++j) {
+        float* dst = gout.sh + (size_t)(j * 3 + ch) * n + i;
+        if (wrote || add)
+          *dst += gsh[j];
+        else
+          *dst = gsh[j];
+      }
+    }
+    wrote = true;
+#pragma unroll
+    for (int c = 0; c < kShViews; ++c) {
+      const float dot = gd[c][0] * d[c][0] + gd[c][1] * d[c][1] + gd[c][2] * d[c][2];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) gmf[k] += (gd[c][k] - d[c][k] * dot) * inv[c];
+    }
+  }
+  if (mf_loaded)
+    for (int k = 0; k < 3; ++k) gout.means[(size_t)k * n + i] += gmf[k];
+  if (!wrote && !add)
+    for (int j = 0; j < nb * 3; ++j) gout.sh[(size_t)j * n + i] = 0.f;
+}
+
 
 }  // namespace
 
@@ -540,13 +723,29 @@ gs_status launch_preprocess_bwd(const ParamsDev& p, const ViewTable& vt, Frame& 
   auto* ac = (float*)f.acc.p;
   auto* rc = (const uint2*)f.rect.p;
   auto* cm = (const uint8_t*)f.clampm.p;
-  switch (p.sh_degree) {
-    case 0: hipLaunchKernelGGL(k_preprocess_bwd<0>, dim3(blocks), dim3(256), 0, s, p, vt, ac, rc, cm, g); break;
-    case 1: hipLaunchKernelGGL(k_preprocess_bwd<1>, dim3(blocks), dim3(256), 0, s, p, vt, ac, rc, cm, g); break;
-    case 2: hipLaunchKernelGGL(k_preprocess_bwd<2>, dim3(blocks), dim3(256), 0, s, p, vt, ac, rc, cm, g); break;
-    default: hipLaunchKernelGGL(k_preprocess_bwd<3>, dim3(blocks), dim3(256), 0, s, p, vt, ac, rc, cm, g); break;
+  auto go = [&](auto kern) {
+    hipLaunchKernelGGL(kern, dim3(blocks), dim3(256), 0, s, p, vt, ac, rc, cm, g);
+  };
+  if (vt.n == 1) {
+    switch (p.sh_degree) {
+      case 0: go(k_preprocess_bwd_one<0>); break;
+      case 1: go(k_preprocess_bwd_one<1>); break;
+      case 2: go(k_preprocess_bwd_one<2>); break;
+      default: go(k_preprocess_bwd_one<3>); break;
+    }
+    GS_LAUNCHED("preprocess_bwd_one");
+    return GS_OK;
   }
-  GS_LAUNCHED("preprocess_bwd");
+  hipLaunchKernelGGL(k_preprocess_bwd_geom, dim3(blocks), dim3(256), 0, s, p, vt,
+                     (const float*)ac, rc, g);
+  GS_LAUNCHED("preprocess_bwd_geom");
+  switch (p.sh_degree) {
+    case 0: go(k_preprocess_bwd_sh<0, 4>); break;
+    case 1: go(k_preprocess_bwd_sh<1, 4>); break;
+    case 2: go(k_preprocess_bwd_sh<2, 4>); break;
+    default: go(k_preprocess_bwd_sh<3, 4>); break;
+  }
+  GS_LAUNCHED("preprocess_bwd_sh");
   return GS_OK;
 }
 

@@ -18,10 +18,12 @@
 // T * rcp(1 - alpha) from the final value (1 - alpha >= 0.01, so the 1-ulp
 // hardware reciprocal is ample), so no per-pixel list is stored.  Each pair
 // yields nine per-lane sums (dpow dx, dpow dy, dpow dx^2, dpow dx dy, dpow dy^2,
-// dalpha G and the three colour weights; the conic is applied to the first two
-// once per (tile, Gaussian) when the sums are flushed).  They are
-// reduce-scattered across the wave (two gfx950 permlane swaps, then three DPP
-// steps inside 16-lane rows: about 25 VALU instructions for all nine), added
+// dpow and the three colour weights; the conic is applied to the first two and
+// the opacity divides the sixth once per (tile, Gaussian) when the sums are
+// flushed).  They are
+// reduce-scattered across the wave (eight by two gfx950 permlane swaps and DPP
+// steps inside 16-lane rows, the ninth by DPP row sums: about 23 VALU
+// instructions for all nine), added
 // across the workgroup's waves with LDS float atomics and to the per-Gaussian
 // accumulators with one global atomic per component per (tile, Gaussian).
 //
@@ -345,44 +347,44 @@ __device__ inline float swap16_sum(float a, float b) {
   return __uint_as_float(r[0]) + __uint_as_float(r[1]);
 }
 
-// Reduce-scatter of nine per-lane values over the wave.  xor-32 pairs leave
-// five values per lane (g0..g4 in lanes 0-31, g5..g8 in 32-63), xor-16 pairs
-// three (row r holds values base + odd, base + 2 + odd and base + 4, with
-// base = 5 (r >> 1) and odd = r & 1).  Inside a 16-lane row the xor-8 step
-// (row_ror:8) merges the first two, the mirror step of each 8-lane half
-// merges that result with the third, and the quad steps finish: lane 0 of the
-// row then holds the row sum of the first value, lane 8 of the second and
-// lane 4 of the third.  lane_slot() names the value a lane ends up owning.
+// Reduce-scatter of nine per-lane values over the wave.  The first eight go
+// through xor-32 pairs (g0..g3 kept by lanes 0-31, g4..g7 by 32-63) and xor-16
+// pairs (row r then holds values (r & 1) + 4 (r >> 1) and that + 2); inside a
+// 16-lane row the xor-8 step (row_ror:8) leaves one value per 8-lane half, and
+// the mirror and two quad steps sum each half, so lane 0 of row r owns the
+// first of the row's values and lane 8 the second.  The ninth is summed over
+// each row by the same four DPP steps and added by the row's last lane (four
+// LDS atomics).  lane_slot() names the value a lane ends up owning.
 __device__ inline int lane_slot(int lane) {
   const int row = lane >> 4, p = lane & 15;
-  const int base = 5 * (row >> 1), odd = row & 1;
-  if (p == 0) return base + odd;
-  if (p == 8) return base + 2 + odd;
-  if (p == 4 && row == 0) return 4;
+  const int base = (row & 1) + 4 * (row >> 1);
+  if (p == 0) return base;
+  if (p == 8) return base + 2;
+  if (p == 15) return 8;
   return -1;
 }
 
-// Adds the wave sums of g[0..8] to part[k] (one LDS atomic per sum); slot is
-// lane_slot(lane).
-__device__ inline void wave_reduce_add(const float* g, float* part, int slot, bool hi8, bool hi4) {
-  const float a0 = swap32_sum(g[0], g[5]);
-  const float a1 = swap32_sum(g[1], g[6]);
-  const float a2 = swap32_sum(g[2], g[7]);
-  const float a3 = swap32_sum(g[3], g[8]);
-  const float a4 = swap32_sum(g[4], 0.f);
+// Adds the wave sums of g[0..8] to part[k] (LDS atomics); slot is
+// lane_slot(lane), hi8 whether bit 3 of the lane index is set.
+__device__ inline void wave_reduce_add(const float* g, float* part, int slot, bool hi8) {
+  const float a0 = swap32_sum(g[0], g[4]);
+  const float a1 = swap32_sum(g[1], g[5]);
+  const float a2 = swap32_sum(g[2], g[6]);
+  const float a3 = swap32_sum(g[3], g[7]);
   const float b0 = swap16_sum(a0, a1);
   const float b1 = swap16_sum(a2, a3);
-  const float b2 = swap16_sum(a4, 0.f);
   // xor 8: lanes 0-7 keep b0 and take the partner's b0, lanes 8-15 likewise b1
-  const float k01 = hi8 ? b1 : b0, s01 = hi8 ? b0 : b1;
-  const float c01 = k01 + dpp_f(s01, 0x128);
-  const float c2 = b2 + dpp_f(b2, 0x128);
-  // mirror within 8 lanes: q < 4 keeps c01, q >= 4 keeps c2
-  const float kd = hi4 ? c2 : c01, sd = hi4 ? c01 : c2;
-  float d = kd + dpp_f(sd, 0x141);
-  d += dpp_f(d, 0x4E);  // quad_perm [2,3,0,1]
-  d += dpp_f(d, 0xB1);  // quad_perm [1,0,3,2]
-  if (slot >= 0 && d != 0.f) atomicAdd(&part[slot], d);
+  const float k = hi8 ? b1 : b0, sx = hi8 ? b0 : b1;
+  float d = k + dpp_f(sx, 0x128);
+  d += dpp_f(d, 0x141);  // row_half_mirror
+  d += dpp_f(d, 0x4E);   // quad_perm [2,3,0,1]
+  d += dpp_f(d, 0xB1);   // quad_perm [1,0,3,2]
+  float e = g[8] + dpp_f(g[8], 0x128);
+  e += dpp_f(e, 0x141);
+  e += dpp_f(e, 0x4E);
+  e += dpp_f(e, 0xB1);
+  const float v = slot == 8 ? e : d;
+  if (slot >= 0 && v != 0.f) atomicAdd(&part[slot], v);
 }
 
 template <int TILE, int DEPTH>
@@ -431,7 +433,7 @@ __device__ inline void bwd_tile(BwdSmem<TILE, DEPTH>& sm, const ViewTable& vt, i
   // (it starts as T_final * bg); dL/dalpha needs S only through this product
   float D = T * (dr * vt.bg[0] + dg * vt.bg[1] + db * vt.bg[2]);
   const int slot = lane_slot(lane);
-  const bool hi8 = (lane & 8) != 0, hi4 = (lane & 4) != 0;
+  const bool hi8 = (lane & 8) != 0;
   // last contributor of the wave and of the tile
   uint32_t m = nc;
 #pragma unroll
@@ -472,9 +474,15 @@ __device__ inline void bwd_tile(BwdSmem<TILE, DEPTH>& sm, const ViewTable& vt, i
       const float G = __builtin_amdgcn_exp2f(p2);
       const float a_raw = s.q0.w * G;
       const float alpha = fminf(kAlphaMax, a_raw);
-      const bool contrib =
-          inside && (uint32_t)(lo + s.j) < nc && !(p2 > 0.f) && !(alpha < kAlphaMin);
-      if (__builtin_amdgcn_ballot_w64(contrib) == 0) return;
+      // nc = 0 outside the image, so the first test also covers the image bounds;
+      // one ballot per comparison keeps the wave test on the comparison masks
+      const bool c_pos = (uint32_t)(lo + s.j) < nc;
+      const bool c_pow = !(p2 > 0.f);
+      const bool c_alpha = !(alpha < kAlphaMin);
+      if ((__builtin_amdgcn_ballot_w64(c_pos) & __builtin_amdgcn_ballot_w64(c_pow) &
+           __builtin_amdgcn_ballot_w64(c_alpha)) == 0)
+        return;
+      const bool contrib = c_pos && c_pow && c_alpha;
       // Gradient arithmetic, branch-free: a lane that does not contribute selects
       // zeros, so its nine values are exactly 0 and its state is unchanged.
       // 1 - alpha >= 0.01, so the hardware reciprocal (1 ulp) is safe here.
@@ -490,7 +498,9 @@ __device__ inline void bwd_tile(BwdSmem<TILE, DEPTH>& sm, const ViewTable& vt, i
       D = fmaf(w, cdot, D);
       // Per-pair sums whose (tile, Gaussian) totals give the screen gradients:
       // dpow dx, dpow dy (mean, after the conic is applied at the flush),
-      // dpow dx^2, dpow dx dy, dpow dy^2 (conic), dalpha G (opacity), w dL/dout.
+      // dpow dx^2, dpow dx dy, dpow dy^2 (conic), dpow (opacity: dL/do is the sum
+      // of dalpha G = dpow / o over unclamped pairs, and dpow is zero on the
+      // others), w dL/dout (colour).
       const float dpow = dalpha * alpha;
       const float ex = dpow * dx, ey = dpow * dy;
       float g[9];
@@ -499,11 +509,11 @@ __device__ inline void bwd_tile(BwdSmem<TILE, DEPTH>& sm, const ViewTable& vt, i
       g[2] = ex * dx;
       g[3] = ex * dy;
       g[4] = ey * dy;
-      g[5] = open ? dalpha * G : 0.f;
+      g[5] = dpow;
       g[6] = w * dr;
       g[7] = w * dg;
       g[8] = w * db;
-      wave_reduce_add(g, &part[s.j * 9], slot, hi8, hi4);
+      wave_reduce_add(g, &part[s.j * 9], slot, hi8);
     };
     // two slots in flight: the LDS reads of one overlap the arithmetic of the other
     if (k >= 0) {
@@ -537,6 +547,8 @@ __device__ inline void bwd_tile(BwdSmem<TILE, DEPTH>& sm, const ViewTable& vt, i
         s = c == 0 ? fmaf(A, e0, B * e1) : fmaf(B, e0, C * e1);
       } else if (c < 5) {
         s *= c == 3 ? -1.f : -0.5f;  // conic: -dpow dx^2 / 2, -dpow dx dy, -dpow dy^2 / 2
+      } else if (c == 5) {
+        s = s / st.s0[j].w;  // opacity: sum of dpow / o
       }
       if (s != 0.f) {
         // AoS accumulators: the nine components of a (view, Gaussian) are adjacent,

@@ -217,23 +217,27 @@ __device__ inline void fwd_tile(Stage<TILE * TILE, DEPTH>& st, const ViewTable& 
   const uint2 rg = ranges[gt];
   float T = 1.f, cr = 0.f, cg = 0.f, cb = 0.f;
   uint32_t last = 0;
-  bool done = !inside;
+  // lanes that have stopped (outside the image or terminated), as a wave mask:
+  // the per-pair decisions are then scalar mask operations on comparison results
+  uint64_t done_m = __builtin_amdgcn_ballot_w64(!inside);
   for (uint32_t base = rg.x; base < rg.y; base += DEPTH) {
-    if (__syncthreads_count(done) == NT) break;
+    if (__syncthreads_count(__builtin_amdgcn_inverse_ballot_w64(done_m)) == NT) break;
     const int cnt = (int)min((uint32_t)DEPTH, rg.y - base);
     stage_batch<TILE, DEPTH>(st, tval, splat, base, cnt, tile_x * TILE, tile_y * TILE);
     const int nw = __builtin_amdgcn_readfirstlane((int)st.count[wave]);
-    if (nw == 0 || !__any(!done)) continue;
+    if (nw == 0 || done_m == ~0ull) continue;
     // Branch-free front-to-back step; a lane that has stopped keeps its state.
     auto step = [&](const Slot& s) {
       float dx, dy;
       const float p2 = pair_eval(s.q0, s.m, rx, ry, dx, dy);
       const float alpha = fminf(kAlphaMax, s.q0.w * __builtin_amdgcn_exp2f(p2));
-      bool use = !done && !(p2 > 0.f) && !(alpha < kAlphaMin);
+      uint64_t m_use = ~done_m & __builtin_amdgcn_ballot_w64(!(p2 > 0.f)) &
+                       __builtin_amdgcn_ballot_w64(!(alpha < kAlphaMin));
       const float Tn = T * (1.f - alpha);
-      const bool stop = use && Tn < kTMin;
-      done = done || stop;
-      use = use && !stop;
+      const uint64_t m_stop = m_use & __builtin_amdgcn_ballot_w64(Tn < kTMin);
+      done_m |= m_stop;
+      m_use &= ~m_stop;
+      const bool use = __builtin_amdgcn_inverse_ballot_w64(m_use);
       const float w = use ? alpha * T : 0.f;
       cr = fmaf(s.q2.x, w, cr);
       cg = fmaf(s.q2.y, w, cg);
@@ -259,7 +263,7 @@ __device__ inline void fwd_tile(Stage<TILE * TILE, DEPTH>& st, const ViewTable& 
         step(a);
         a = load_slot(st, list_at(chunk, min(kk + 4, n - 1)));
         step(b);
-        if ((kk & 4) != 0 && !__any(!done)) {  // every 8 slots
+        if ((kk & 4) != 0 && done_m == ~0ull) {  // every 8 slots
           all_done = true;
           break;
         }
@@ -269,7 +273,7 @@ __device__ inline void fwd_tile(Stage<TILE * TILE, DEPTH>& st, const ViewTable& 
         step(a);
         a = b;
       }
-      all_done = all_done || !__any(!done);
+      all_done = all_done || done_m == ~0ull;
     }
   }
   if (inside) {

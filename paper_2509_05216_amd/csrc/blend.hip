@@ -98,7 +98,10 @@ struct Stage {
   float4 s1[DEPTH];  // mean relative to the tile origin (x, y), unused (z, w)
   float4 s2[DEPTH];  // rgb
   uint32_t sidx[DEPTH];
-  uint16_t list[NW][DEPTH];
+  // per wave: byte offsets (16 x slot) of the overlapping slots in ascending
+  // order, then four zero entries, so that reads of up to four entries past the
+  // end stay valid; 16-byte aligned for four-entry reads
+  alignas(16) uint32_t list[NW][DEPTH + 4];
   uint32_t chunk[NW][DEPTH / 64 + 1];
   uint32_t count[NW];
 };
@@ -144,12 +147,14 @@ __device__ inline void stage_batch(Stage<TILE * TILE, DEPTH>& st, const uint32_t
       if ((mask >> w) & 1u) {
         uint32_t off = rank[w];
         for (int c = 0; c < wave; ++c) off += st.chunk[w][c];
-        st.list[w][off] = (uint16_t)t;
+        st.list[w][off] = (uint32_t)t * 16u;
       }
       if (t == 0) {
         uint32_t tot = 0;
         for (int c = 0; c < (DEPTH + 63) / 64; ++c) tot += st.chunk[w][c];
         st.count[w] = tot;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) st.list[w][tot + u] = 0u;
       }
     }
   }
@@ -169,31 +174,25 @@ struct Layout {
   }
 };
 
-// A wave's compacted slot list is walked 64 entries at a time: one LDS read
-// puts entries [c0, c0 + 64) in a VGPR (one per lane) and the entry at a
-// wave-uniform position comes back as a scalar through readlane, so the walk
-// needs no LDS round trip per slot for its index.
-__device__ inline int list_chunk(const uint16_t* row, int c0, int depth) {
-  return row[min(c0 + (int)__lane_id(), depth - 1)];
-}
-
-__device__ inline int list_at(int chunk, int kk) { return __builtin_amdgcn_readlane(chunk, kk & 63); }
-
 // Operands of one staged splat, read from LDS (same address in every lane).
+// The walks take slot byte offsets straight from the wave's list (LDS reads
+// of several entries at once into VGPRs, used as addresses as they are).
 struct Slot {
-  int j;
-  float4 q0;  // scaled conic, opacity
-  float2 m;   // tile-relative mean
-  float3 q2;  // rgb
+  uint32_t off;  // 16 x slot index
+  float4 q0;     // scaled conic, opacity
+  float2 m;      // tile-relative mean
+  float3 q2;     // rgb
 };
 
 template <int NT, int DEPTH>
-__device__ inline Slot load_slot(const Stage<NT, DEPTH>& st, int j) {
+__device__ inline Slot load_slot(const Stage<NT, DEPTH>& st, uint32_t off) {
   Slot s;
-  s.j = j;
-  s.q0 = st.s0[j];
-  s.m = make_float2(st.s1[j].x, st.s1[j].y);
-  s.q2 = make_float3(st.s2[j].x, st.s2[j].y, st.s2[j].z);
+  s.off = off;
+  s.q0 = *reinterpret_cast<const float4*>(reinterpret_cast<const char*>(st.s0) + off);
+  const float4 m = *reinterpret_cast<const float4*>(reinterpret_cast<const char*>(st.s1) + off);
+  s.m = make_float2(m.x, m.y);
+  const float4 c = *reinterpret_cast<const float4*>(reinterpret_cast<const char*>(st.s2) + off);
+  s.q2 = make_float3(c.x, c.y, c.z);
   return s;
 }
 
@@ -227,6 +226,8 @@ __device__ inline void fwd_tile(Stage<TILE * TILE, DEPTH>& st, const ViewTable& 
     const int nw = __builtin_amdgcn_readfirstlane((int)st.count[wave]);
     if (nw == 0 || done_m == ~0ull) continue;
     // Branch-free front-to-back step; a lane that has stopped keeps its state.
+    // last_off: list offset of this batch's last record used by the lane
+    uint32_t last_off = ~0u;
     auto step = [&](const Slot& s) {
       float dx, dy;
       const float p2 = pair_eval(s.q0, s.m, rx, ry, dx, dy);
@@ -243,38 +244,45 @@ __device__ inline void fwd_tile(Stage<TILE * TILE, DEPTH>& st, const ViewTable& 
       cg = fmaf(s.q2.y, w, cg);
       cb = fmaf(s.q2.z, w, cb);
       T = use ? Tn : T;
-      last = use ? base + (uint32_t)s.j - rg.x + 1u : last;
+      last_off = use ? s.off : last_off;
     };
-    const uint16_t* row = st.list[wave];
+    const uint32_t* row = st.list[wave];
+    // entries kk .. kk + 3 in one read; two slots in flight (the LDS reads of
+    // one overlap the arithmetic of the other), four per iteration
+    uint4 e = *reinterpret_cast<const uint4*>(row);
+    Slot a = load_slot(st, e.x);
+    int kk = 0;
     bool all_done = false;
-    for (int c0 = 0; c0 < nw && !all_done; c0 += 64) {
-      const int chunk = list_chunk(row, c0, DEPTH);
-      const int n = min(64, nw - c0);
-      // two slots in flight (the LDS reads of one overlap the arithmetic of the
-      // other), four per iteration
-      Slot a = load_slot(st, list_at(chunk, 0));
-      int kk = 0;
-      for (; kk + 3 < n; kk += 4) {
-        Slot b = load_slot(st, list_at(chunk, kk + 1));
-        step(a);
-        a = load_slot(st, list_at(chunk, kk + 2));
-        step(b);
-        b = load_slot(st, list_at(chunk, kk + 3));
-        step(a);
-        a = load_slot(st, list_at(chunk, min(kk + 4, n - 1)));
-        step(b);
-        if ((kk & 4) != 0 && done_m == ~0ull) {  // every 8 slots
-          all_done = true;
-          break;
-        }
+    for (; kk + 3 < nw; kk += 4) {
+      const uint4 en = *reinterpret_cast<const uint4*>(row + kk + 4);  // <= nw + 3: padded
+      Slot b = load_slot(st, e.y);
+      step(a);
+      a = load_slot(st, e.z);
+      step(b);
+      b = load_slot(st, e.w);
+      step(a);
+      a = load_slot(st, en.x);
+      step(b);
+      e = en;
+      if ((kk & 4) != 0 && done_m == ~0ull) {  // every 8 slots
+        all_done = true;
+        break;
       }
-      for (; kk < n && !all_done; ++kk) {  // up to three left; a holds entry kk
-        const Slot b = load_slot(st, list_at(chunk, min(kk + 1, n - 1)));
+    }
+    if (!all_done) {  // up to three left: e holds entries kk .. kk + 3, a entry kk
+      if (kk < nw) {
+        const Slot b = load_slot(st, e.y);
         step(a);
         a = b;
       }
-      all_done = all_done || done_m == ~0ull;
+      if (kk + 1 < nw) {
+        const Slot b = load_slot(st, e.z);
+        step(a);
+        a = b;
+      }
+      if (kk + 2 < nw) step(a);
     }
+    if (last_off != ~0u) last = base - rg.x + 1u + (last_off >> 4);
   }
   if (inside) {
     const size_t pix = (size_t)py * cam.W + px;
@@ -368,9 +376,10 @@ __device__ inline int lane_slot(int lane) {
   return -1;
 }
 
-// Adds the wave sums of g[0..8] to part[k] (LDS atomics); slot is
-// lane_slot(lane), hi8 whether bit 3 of the lane index is set.
-__device__ inline void wave_reduce_add(const float* g, float* part, int slot, bool hi8) {
+// Adds the wave sums of g[0..8] to the sum table (LDS atomics): the lane that
+// owns sum k (slot = lane_slot(lane) = k) adds it at dst, its address for k;
+// hi8: bit 3 of the lane index.
+__device__ inline void wave_reduce_add(const float* g, float* dst, int slot, bool hi8) {
   const float a0 = swap32_sum(g[0], g[4]);
   const float a1 = swap32_sum(g[1], g[5]);
   const float a2 = swap32_sum(g[2], g[6]);
@@ -388,13 +397,14 @@ __device__ inline void wave_reduce_add(const float* g, float* part, int slot, bo
   e += dpp_f(e, 0x4E);
   e += dpp_f(e, 0xB1);
   const float v = slot == 8 ? e : d;
-  if (slot >= 0 && v != 0.f) atomicAdd(&part[slot], v);
+  if (slot >= 0 && v != 0.f) atomicAdd(dst, v);
 }
 
 template <int TILE, int DEPTH>
 struct BwdSmem {
+  static constexpr int kPart = DEPTH + 1;  // row of the sum table (odd: no bank conflicts)
   Stage<TILE * TILE, DEPTH> st;
-  float part[DEPTH * 9];
+  float part[9 * kPart];  // sum c of slot j at c * kPart + j
   uint32_t smax[TILE * TILE / 64];
 };
 
@@ -438,6 +448,9 @@ __device__ inline void bwd_tile(BwdSmem<TILE, DEPTH>& sm, const ViewTable& vt, i
   float D = T * (dr * vt.bg[0] + dg * vt.bg[1] + db * vt.bg[2]);
   const int slot = lane_slot(lane);
   const bool hi8 = (lane & 8) != 0;
+  constexpr int kPart = BwdSmem<TILE, DEPTH>::kPart;
+  // this lane's sum row (slot >= 0); the slot's column is added per pair
+  float* const part_lane = part + (slot >= 0 ? slot : 0) * kPart;
   // last contributor of the wave and of the tile
   uint32_t m = nc;
 #pragma unroll
@@ -452,23 +465,25 @@ __device__ inline void bwd_tile(BwdSmem<TILE, DEPTH>& sm, const ViewTable& vt, i
     const int lo = max(0, hi - DEPTH);
     const int cnt = hi - lo;
     __syncthreads();
-    for (int j = threadIdx.x; j < cnt * 9; j += NT) part[j] = 0.f;
+    for (int j = threadIdx.x; j < 9 * kPart; j += NT) part[j] = 0.f;
     stage_batch<TILE, DEPTH>(st, tval, splat, rg.x + (uint32_t)lo, cnt, tile_x * TILE,
                              tile_y * TILE);
     // walk this wave's overlapping slots from the back, below its last contributor
     // entries of this wave's list below its last contributor: the list is
     // ascending, so they are a prefix, counted by ballots over its chunks
-    const uint16_t* row = st.list[wave];
+    const uint32_t* row = st.list[wave];
     const int cw = __builtin_amdgcn_readfirstlane((int)st.count[wave]);
     int nuse = 0;
     if (lo < wave_n) {
       for (int c0 = 0; c0 < cw; c0 += 64) {
         const int e = c0 + (int)__lane_id();
-        const bool below = e < cw && lo + (int)row[min(e, DEPTH - 1)] < wave_n;
+        const bool below = e < cw && lo + (int)(row[min(e, DEPTH - 1)] >> 4) < wave_n;
         nuse += (int)__popcll(__ballot(below));
       }
     }
     int k = nuse - 1;
+    // lo + j < nc as a comparison of list offsets: 16 j < 16 (nc - lo)
+    const uint32_t ncb = nc > (uint32_t)lo ? min(nc - (uint32_t)lo, (uint32_t)DEPTH) * 16u : 0u;
     // One pair (this lane's pixel, slot s) of the reverse walk.
     auto pair = [&](const Slot& s) {
       const float3 q2 = s.q2;
@@ -480,7 +495,7 @@ __device__ inline void bwd_tile(BwdSmem<TILE, DEPTH>& sm, const ViewTable& vt, i
       const float alpha = fminf(kAlphaMax, a_raw);
       // nc = 0 outside the image, so the first test also covers the image bounds;
       // one ballot per comparison keeps the wave test on the comparison masks
-      const bool c_pos = (uint32_t)(lo + s.j) < nc;
+      const bool c_pos = s.off < ncb;
       const bool c_pow = !(p2 > 0.f);
       const bool c_alpha = !(alpha < kAlphaMin);
       if ((__builtin_amdgcn_ballot_w64(c_pos) & __builtin_amdgcn_ballot_w64(c_pow) &
@@ -517,37 +532,42 @@ __device__ inline void bwd_tile(BwdSmem<TILE, DEPTH>& sm, const ViewTable& vt, i
       g[6] = w * dr;
       g[7] = w * dg;
       g[8] = w * db;
-      wave_reduce_add(g, &part[s.j * 9], slot, hi8);
+      wave_reduce_add(g, part_lane + (s.off >> 4), slot, hi8);
     };
-    // two slots in flight: the LDS reads of one overlap the arithmetic of the other
+    // two slots in flight: the LDS reads of one overlap the arithmetic of the
+    // other; list entries two at a time (k - 1, k with k odd: 8-byte aligned)
     if (k >= 0) {
-      int c0 = k & ~63;
-      int chunk = list_chunk(row, c0, DEPTH);
       if ((k & 1) == 0) {  // odd count: the top entry alone, then pairs (k, k - 1)
-        pair(load_slot(st, list_at(chunk, k)));
+        pair(load_slot(st, row[k]));
         --k;
-        if (k >= 0 && (k & 63) == 63) chunk = list_chunk(row, c0 -= 64, DEPTH);
       }
-      // k is odd here, so k and k - 1 share a chunk; two slots in flight
-      Slot a = load_slot(st, list_at(chunk, max(k, 0)));
-      while (k >= 1) {
-        const Slot b = load_slot(st, list_at(chunk, k - 1));
-        pair(a);
-        k -= 2;
-        if (k >= 0 && (k & 63) == 63) chunk = list_chunk(row, c0 -= 64, DEPTH);
-        a = load_slot(st, list_at(chunk, max(k, 0)));
-        pair(b);
+      if (k >= 1) {
+        uint2 e = *reinterpret_cast<const uint2*>(row + k - 1);  // entries k - 1, k
+        Slot a = load_slot(st, e.y);
+        for (;;) {
+          const Slot b = load_slot(st, e.x);
+          const uint2 en = *reinterpret_cast<const uint2*>(row + max(k - 3, 0));
+          pair(a);
+          k -= 2;
+          if (k < 1) {
+            pair(b);
+            break;
+          }
+          a = load_slot(st, en.y);
+          pair(b);
+          e = en;
+        }
       }
     }
     __syncthreads();
     for (int t = threadIdx.x; t < cnt * 9; t += NT) {
       const int j = t / 9, c = t - j * 9;
-      float s = part[t];
+      float s = part[c * kPart + j];
       if (c < 2) {
         // mean: (A dx + B dy, B dx + C dy) dpow summed = conic applied to the sums
         const float4 q = st.s0[j];
         const float A = q.x * (-2.f * kLn2), B = q.y * -kLn2, C = q.z * (-2.f * kLn2);
-        const float e0 = part[j * 9], e1 = part[j * 9 + 1];
+        const float e0 = part[j], e1 = part[kPart + j];
         s = c == 0 ? fmaf(A, e0, B * e1) : fmaf(B, e0, C * e1);
       } else if (c < 5) {
         s *= c == 3 ? -1.f : -0.5f;  // conic: -dpow dx^2 / 2, -dpow dx dy, -dpow dy^2 / 2

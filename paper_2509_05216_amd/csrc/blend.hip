@@ -95,7 +95,7 @@ struct Stage {
   static constexpr int NW = NT / 64;
   // 16 bytes per slot in every array, so one shifted index addresses all three
   float4 s0[DEPTH];  // scaled conic (a, b, c), opacity
-  float4 s1[DEPTH];  // mean relative to the tile origin (x, y), unused (z, w)
+  float4 s1[DEPTH];  // mean relative to the tile origin (x, y), 4 x slot as bits (z), unused (w)
   float4 s2[DEPTH];  // rgb
   uint32_t sidx[DEPTH];
   // per wave: byte offsets (16 x slot) of the overlapping slots in ascending
@@ -123,7 +123,8 @@ __device__ inline void stage_batch(Stage<TILE * TILE, DEPTH>& st, const uint32_t
     st.sidx[t] = idx;
     st.s0[t] = make_float4(q0.x * (-0.5f * kLog2e), q0.y * -kLog2e, q0.z * (-0.5f * kLog2e), q0.w);
     st.s1[t] = make_float4((float)(__float_as_int(q1.x) - tile_x0) - q1.z,
-                           (float)(__float_as_int(q1.y) - tile_y0) - q1.w, 0.f, 0.f);
+                           (float)(__float_as_int(q1.y) - tile_y0) - q1.w,
+                           __uint_as_float((uint32_t)t * 4u), 0.f);
     st.s2[t] = q2;  // rgb; the walks do not read .w (the packed box)
     const float4 b = splat_box(q1, q2);
 #pragma unroll
@@ -178,10 +179,11 @@ struct Layout {
 // The walks take slot byte offsets straight from the wave's list (LDS reads
 // of several entries at once into VGPRs, used as addresses as they are).
 struct Slot {
-  uint32_t off;  // 16 x slot index
-  float4 q0;     // scaled conic, opacity
-  float2 m;      // tile-relative mean
-  float3 q2;     // rgb
+  uint32_t off;   // 16 x slot index
+  uint32_t off4;  // 4 x slot index (byte offset of the slot's column in the sum table)
+  float4 q0;      // scaled conic, opacity
+  float2 m;       // tile-relative mean
+  float3 q2;      // rgb
 };
 
 template <int NT, int DEPTH>
@@ -191,6 +193,7 @@ __device__ inline Slot load_slot(const Stage<NT, DEPTH>& st, uint32_t off) {
   s.q0 = *reinterpret_cast<const float4*>(reinterpret_cast<const char*>(st.s0) + off);
   const float4 m = *reinterpret_cast<const float4*>(reinterpret_cast<const char*>(st.s1) + off);
   s.m = make_float2(m.x, m.y);
+  s.off4 = __float_as_uint(m.z);
   const float4 c = *reinterpret_cast<const float4*>(reinterpret_cast<const char*>(st.s2) + off);
   s.q2 = make_float3(c.x, c.y, c.z);
   return s;
@@ -482,8 +485,8 @@ __device__ inline void bwd_tile(BwdSmem<TILE, DEPTH>& sm, const ViewTable& vt, i
       }
     }
     int k = nuse - 1;
-    // lo + j < nc as a comparison of list offsets: 16 j < 16 (nc - lo)
-    const uint32_t ncb = nc > (uint32_t)lo ? min(nc - (uint32_t)lo, (uint32_t)DEPTH) * 16u : 0u;
+    // lo + j < nc as a comparison of sum-table offsets: 4 j < 4 (nc - lo)
+    const uint32_t ncb = nc > (uint32_t)lo ? min(nc - (uint32_t)lo, (uint32_t)DEPTH) * 4u : 0u;
     // One pair (this lane's pixel, slot s) of the reverse walk.
     auto pair = [&](const Slot& s) {
       const float3 q2 = s.q2;
@@ -495,7 +498,7 @@ __device__ inline void bwd_tile(BwdSmem<TILE, DEPTH>& sm, const ViewTable& vt, i
       const float alpha = fminf(kAlphaMax, a_raw);
       // nc = 0 outside the image, so the first test also covers the image bounds;
       // one ballot per comparison keeps the wave test on the comparison masks
-      const bool c_pos = s.off < ncb;
+      const bool c_pos = s.off4 < ncb;
       const bool c_pow = !(p2 > 0.f);
       const bool c_alpha = !(alpha < kAlphaMin);
       if ((__builtin_amdgcn_ballot_w64(c_pos) & __builtin_amdgcn_ballot_w64(c_pow) &
@@ -532,7 +535,8 @@ __device__ inline void bwd_tile(BwdSmem<TILE, DEPTH>& sm, const ViewTable& vt, i
       g[6] = w * dr;
       g[7] = w * dg;
       g[8] = w * db;
-      wave_reduce_add(g, part_lane + (s.off >> 4), slot, hi8);
+      wave_reduce_add(g, reinterpret_cast<float*>(reinterpret_cast<char*>(part_lane) + s.off4),
+                      slot, hi8);
     };
     // two slots in flight: the LDS reads of one overlap the arithmetic of the
     // other; list entries two at a time (k - 1, k with k odd: 8-byte aligned)

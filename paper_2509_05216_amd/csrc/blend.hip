@@ -250,29 +250,53 @@ __device__ inline void fwd_tile(Stage<TILE * TILE, DEPTH>& st, const ViewTable& 
       last_off = use ? s.off : last_off;
     };
     const uint32_t* row = st.list[wave];
+    auto entries = [&](int k) { return *reinterpret_cast<const uint4*>(row + k); };
     // entries kk .. kk + 3 in one read; two slots in flight (the LDS reads of
-    // one overlap the arithmetic of the other), four per iteration
-    uint4 e = *reinterpret_cast<const uint4*>(row);
+    // one overlap the arithmetic of the other), eight per iteration
+    uint4 e = entries(0);
     Slot a = load_slot(st, e.x);
     int kk = 0;
     bool all_done = false;
-    for (; kk + 3 < nw; kk += 4) {
-      const uint4 en = *reinterpret_cast<const uint4*>(row + kk + 4);  // <= nw + 3: padded
+    for (; kk + 7 < nw; kk += 8) {
+      const uint4 e1 = entries(kk + 4);
       Slot b = load_slot(st, e.y);
       step(a);
       a = load_slot(st, e.z);
       step(b);
       b = load_slot(st, e.w);
       step(a);
-      a = load_slot(st, en.x);
+      a = load_slot(st, e1.x);
       step(b);
-      e = en;
-      if ((kk & 4) != 0 && done_m == ~0ull) {  // every 8 slots
+      const uint4 e2 = entries(kk + 8);  // <= nw + 3: padded
+      b = load_slot(st, e1.y);
+      step(a);
+      a = load_slot(st, e1.z);
+      step(b);
+      b = load_slot(st, e1.w);
+      step(a);
+      a = load_slot(st, e2.x);
+      step(b);
+      e = e2;
+      if (done_m == ~0ull) {
         all_done = true;
         break;
       }
     }
-    if (!all_done) {  // up to three left: e holds entries kk .. kk + 3, a entry kk
+    if (!all_done) {
+      if (kk + 3 < nw) {  // four more
+        const uint4 e1 = entries(kk + 4);
+        Slot b = load_slot(st, e.y);
+        step(a);
+        a = load_slot(st, e.z);
+        step(b);
+        b = load_slot(st, e.w);
+        step(a);
+        a = load_slot(st, e1.x);
+        step(b);
+        e = e1;
+        kk += 4;
+      }
+      // up to three left: e holds entries kk .. kk + 3, a entry kk
       if (kk < nw) {
         const Slot b = load_slot(st, e.y);
         step(a);

@@ -243,7 +243,10 @@ gs_status gs_bw_probe(gs_ctx* ctx, const void* src, void* dst, size_t bytes, voi
 
 gs_status gs_frame_stats_get(gs_frame* frame, gs_frame_stats* out);
 /* Copy a frame buffer (see gs_export) for view `view` (-1 = all views) into
- * the caller's device buffer dst of `bytes` bytes (must be large enough). */
+ * the caller's device buffer dst of `bytes` bytes (must be large enough;
+ * GS_EXPORT_SCREEN_GRADS also needs dst 16-byte aligned).  Errors:
+ * GS_ERR_INVALID for a null frame or dst, a view out of range, an unknown
+ * export, a short or misaligned dst. */
 gs_status gs_frame_export(gs_frame* frame, int32_t what, int32_t view, void* dst,
                           size_t bytes, void* stream);
 void gs_frame_release(gs_frame* frame);

@@ -878,13 +878,14 @@ gs_status gs_frame_export(gs_frame* frame, int32_t what, int32_t view, void* dst
       }
       break;
     case GS_EXPORT_SCREEN_GRADS:
-      src = f.acc.p;
-      need = (size_t)f.views * kAccStride * n * 4;
-      if (view >= 0) {
-        off = (size_t)view * kAccStride * n * 4;
-        need = kAccStride * n * 4;
+      // interleaved from the geometric and colour accumulators by a kernel
+      need = (size_t)(view >= 0 ? 1 : f.views) * 12 * n * 4;
+      if (bytes < need) break;
+      if (((uintptr_t)dst & 15u) != 0) {
+        set_error("gs_frame_export: screen gradients need a 16-byte aligned destination");
+        return GS_ERR_INVALID;
       }
-      break;
+      return launch_export_screen_grads(f, view, (float*)dst, s);
     case GS_EXPORT_SPLATS:
       src = f.splat.p;
       need = (size_t)f.views * n * 48;

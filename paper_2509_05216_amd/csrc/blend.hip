@@ -442,7 +442,8 @@ __device__ inline void bwd_tile(BwdSmem<TILE, DEPTH>& sm, const ViewTable& vt, i
                                 const uint32_t* __restrict__ tval,
                                 const float4* __restrict__ splat,
                                 const float* __restrict__ finalT,
-                                const uint32_t* __restrict__ ncon, float* __restrict__ acc) {
+                                const uint32_t* __restrict__ ncon, float* __restrict__ accG,
+                                float* __restrict__ accC) {
   constexpr int NT = TILE * TILE;
   constexpr int NW = NT / 64;
   Stage<NT, DEPTH>& st = sm.st;
@@ -603,9 +604,14 @@ __device__ inline void bwd_tile(BwdSmem<TILE, DEPTH>& sm, const ViewTable& vt, i
         s = s / st.s0[j].w;  // opacity: sum of dpow / o
       }
       if (s != 0.f) {
-        // AoS accumulators: the nine components of a (view, Gaussian) are adjacent,
-        // so neighbouring lanes' atomics fall in one or two cache lines
-        atomicAdd(acc + (size_t)st.sidx[j] * kAccStride + c, s);
+        // record-major accumulators: the six geometric sums of a (view, Gaussian)
+        // share one 32-byte record and its colour sums one 16-byte record, so
+        // neighbouring lanes' atomics fall in few cache lines
+        const size_t o = st.sidx[j];
+        if (c < 6)
+          atomicAdd(accG + o * kAccG + c, s);
+        else
+          atomicAdd(accC + o * kAccC + (c - 6), s);
       }
     }
   }
@@ -620,23 +626,24 @@ __global__ __launch_bounds__(TILE* TILE) __attribute__((amdgpu_waves_per_eu(6)))
                                                           const float4* __restrict__ splat,
                                                           const float* __restrict__ finalT,
                                                           const uint32_t* __restrict__ ncon,
-                                                          float* __restrict__ acc) {
+                                                          float* __restrict__ accG,
+                                                          float* __restrict__ accC) {
   __shared__ BwdSmem<TILE, DEPTH> sm;
-  bwd_tile<TILE, DEPTH>(sm, vt, blockIdx.x, ranges, tval, splat, finalT, ncon, acc);
+  bwd_tile<TILE, DEPTH>(sm, vt, blockIdx.x, ranges, tval, splat, finalT, ncon, accG, accC);
 }
 
 template <int TILE, int DEPTH>
 __global__ __launch_bounds__(TILE* TILE) __attribute__((amdgpu_waves_per_eu(6))) void k_blend_bwd_persistent(
     ViewTable vt, const uint2* __restrict__ ranges, const uint32_t* __restrict__ tval,
     const float4* __restrict__ splat, const float* __restrict__ finalT,
-    const uint32_t* __restrict__ ncon, float* __restrict__ acc, const uint32_t* __restrict__ order,
-    uint32_t* counter) {
+    const uint32_t* __restrict__ ncon, float* __restrict__ accG, float* __restrict__ accC,
+    const uint32_t* __restrict__ order, uint32_t* counter) {
   __shared__ BwdSmem<TILE, DEPTH> sm;
   __shared__ uint32_t slot;
   for (;;) {
     const int gt = next_tile(counter, order, vt.total_tiles, &slot);
     if (gt < 0) break;
-    bwd_tile<TILE, DEPTH>(sm, vt, gt, ranges, tval, splat, finalT, ncon, acc);
+    bwd_tile<TILE, DEPTH>(sm, vt, gt, ranges, tval, splat, finalT, ncon, accG, accC);
   }
 }
 
@@ -671,12 +678,14 @@ gs_status fwd_t(const ViewTable& vt, Frame& f, hipStream_t s) {
 
 template <int TILE, int DEPTH>
 gs_status bwd_t(const ViewTable& vt, Frame& f, hipStream_t s) {
+  float* accG = (float*)f.acc.p;
+  float* accC = accG + (size_t)f.views * (size_t)f.n * kAccG;
   if (f.persistent) {
     auto kern = k_blend_bwd_persistent<TILE, DEPTH>;
     const int grid = std::min(resident_grid(kern, TILE * TILE, f.ctx), vt.total_tiles);
     hipLaunchKernelGGL(kern, dim3(grid), dim3(TILE * TILE), 0, s, vt, (const uint2*)f.ranges.p,
                        (const uint32_t*)f.tval[f.tkey_sel].p, (const float4*)f.splat.p,
-                       (const float*)f.finalT.p, (const uint32_t*)f.ncon.p, (float*)f.acc.p,
+                       (const float*)f.finalT.p, (const uint32_t*)f.ncon.p, accG, accC,
                        f.tile_order, (uint32_t*)f.words.p + kWordBwdCounter);
     GS_LAUNCHED("blend_bwd_persistent");
     return GS_OK;
@@ -684,9 +693,23 @@ gs_status bwd_t(const ViewTable& vt, Frame& f, hipStream_t s) {
   hipLaunchKernelGGL((k_blend_bwd<TILE, DEPTH>), dim3(vt.total_tiles), dim3(TILE * TILE), 0, s,
                      vt, (const uint2*)f.ranges.p, (const uint32_t*)f.tval[f.tkey_sel].p,
                      (const float4*)f.splat.p, (const float*)f.finalT.p,
-                     (const uint32_t*)f.ncon.p, (float*)f.acc.p);
+                     (const uint32_t*)f.ncon.p, accG, accC);
   GS_LAUNCHED("blend_bwd");
   return GS_OK;
+}
+
+__global__ __launch_bounds__(256) void k_export_screen_grads(const float* __restrict__ accG,
+                                                             const float* __restrict__ accC,
+                                                             size_t count, float* __restrict__ dst) {
+  const size_t r = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+  if (r >= count) return;
+  const float4 g0 = reinterpret_cast<const float4*>(accG)[2 * r];
+  const float4 g1 = reinterpret_cast<const float4*>(accG)[2 * r + 1];
+  const float4 c = reinterpret_cast<const float4*>(accC)[r];
+  float4* o = reinterpret_cast<float4*>(dst) + 3 * r;
+  o[0] = g0;
+  o[1] = make_float4(g1.x, g1.y, c.x, c.y);
+  o[2] = make_float4(c.z, 0.f, 0.f, 0.f);
 }
 
 #define GS_DISPATCH(FN, tile, depth, ...)                                   \
@@ -714,6 +737,22 @@ gs_status launch_blend_fwd(const ViewTable& vt, Frame& f, hipStream_t s) {
 
 gs_status launch_blend_bwd(const ViewTable& vt, Frame& f, hipStream_t s) {
   GS_DISPATCH(bwd_t, f.tile, f.depth, vt, f, s)
+}
+
+gs_status launch_export_screen_grads(Frame& f, int view, float* dst, hipStream_t s) {
+  const size_t n = (size_t)f.n;
+  const float* accG = (const float*)f.acc.p;
+  const float* accC = accG + (size_t)f.views * n * kAccG;
+  size_t first = 0, count = (size_t)f.views * n;
+  if (view >= 0) {
+    first = (size_t)view * n;
+    count = n;
+  }
+  if (count == 0) return GS_OK;
+  hipLaunchKernelGGL(k_export_screen_grads, dim3((unsigned)((count + 255) / 256)), dim3(256), 0,
+                     s, accG + first * kAccG, accC + first * kAccC, count, dst);
+  GS_LAUNCHED("export_screen_grads");
+  return GS_OK;
 }
 
 }  // namespace isogs

@@ -28,9 +28,14 @@
 namespace isogs {
 
 constexpr int kMaxViews = 16;
-// Screen-gradient accumulator record: dL/d(mx, my, A, B, C, opacity, r, g, b) + 3 pad floats,
-// one record per (view, Gaussian), 16-byte aligned.
-constexpr int kAccStride = 12;
+// Screen-gradient accumulators, one record per (view, Gaussian) in each of two
+// arrays held in one allocation: the geometric sums dL/d(mx, my, A, B, C,
+// opacity) + 2 pad floats, then (after all geometric records) the colour sums
+// dL/d(r, g, b) + 1 pad float.  The projection backward's geometry and colour
+// kernels each read (and clear) only their own array.
+constexpr int kAccG = 8;
+constexpr int kAccC = 4;
+constexpr int kAccStride = kAccG + kAccC;  // floats per (view, Gaussian) in total
 
 // Frame-owned device words (u32 slots; 64-bit values at even slots).
 enum Word {
@@ -252,6 +257,9 @@ gs_status launch_export_keys(Frame& f, uint64_t* dst, hipStream_t s);
 // blend.hip
 gs_status launch_blend_fwd(const ViewTable& vt, Frame& f, hipStream_t s);
 gs_status launch_blend_bwd(const ViewTable& vt, Frame& f, hipStream_t s);
+// Screen gradients of view `view` (all views: -1) in the exported layout,
+// float[.][n][12]: the six geometric sums, the three colour sums, 3 zero pads.
+gs_status launch_export_screen_grads(Frame& f, int view, float* dst, hipStream_t s);
 // loss.hip
 gs_status launch_loss(Ctx* ctx, const float* const* x, const float* const* y, const int* W,
                       const int* H, int nv, float lambda, float* loss_out, float* const* dl,

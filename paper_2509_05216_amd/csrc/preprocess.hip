@@ -424,8 +424,7 @@ __device__ inline void geom_body(const ParamsDev& prm, int i, float* mu, float* 
 }
 
 __global__ __launch_bounds__(256) void k_preprocess_bwd_geom(ParamsDev prm, ViewTable vt,
-                                                             const float* __restrict__ acc,
-                                                             const uint2* __restrict__ rect,
+                                                             float* __restrict__ accG,
                                                              GradsDev gout) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int n = prm.n;
@@ -435,13 +434,14 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd_geom(ParamsDev prm, View
   float g_mu[3] = {0.f, 0.f, 0.f}, g_op = 0.f;
   float Gs[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   for (int v = 0; v < vt.n; ++v) {
-    const size_t o = (size_t)v * n + i;
-    const uint2 rc = rect[o];
-    if ((rc.y & 0xffffu) < (rc.x & 0xffffu)) continue;  // untouched in this view
-    const float4* a = reinterpret_cast<const float4*>(acc + o * kAccStride);
+    // untouched (view, Gaussian) entries, and touched ones without gradient, are zero
+    float4* a = reinterpret_cast<float4*>(accG + ((size_t)v * n + i) * kAccG);
     const float4 a0 = a[0], a1 = a[1];
     if (a0.x == 0.f && a0.y == 0.f && a0.z == 0.f && a0.w == 0.f && a1.x == 0.f && a1.y == 0.f)
       continue;
+    // leave the accumulator cleared for the next backward pass
+    a[0] = make_float4(0.f, 0.f, 0.f, 0.f);
+    a[1] = make_float4(0.f, 0.f, 0.f, 0.f);
     if (!loaded) {
       geom_body(prm, i, mu, Sig);
       loaded = true;
@@ -469,8 +469,8 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd_geom(ParamsDev prm, View
 // gradient (Y_j times the colour gradient) is stored as soon as it is formed.
 template <int DEG>
 __global__ __launch_bounds__(256) void k_preprocess_bwd_one(ParamsDev prm, ViewTable vt,
-                                                            float* __restrict__ acc,
-                                                            const uint2* __restrict__ rect,
+                                                            float* __restrict__ accG,
+                                                            float* __restrict__ accC,
                                                             const uint8_t* __restrict__ clampm,
                                                             GradsDev gout) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -483,28 +483,27 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd_one(ParamsDev prm, ViewT
   float Gs[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   bool geo = false, col = false;
   float gr[3] = {0.f, 0.f, 0.f};
-  const uint2 rc = rect[i];
-  if ((rc.y & 0xffffu) >= (rc.x & 0xffffu)) {
-    float4* a = reinterpret_cast<float4*>(acc + (size_t)i * kAccStride);
-    const float4 a0 = a[0], a1 = a[1], a2 = a[2];
+  {
+    // untouched entries, and touched ones without gradient, are zero
+    float4* a = reinterpret_cast<float4*>(accG + (size_t)i * kAccG);
+    float4* ac = reinterpret_cast<float4*>(accC + (size_t)i * kAccC);
+    const float4 a0 = a[0], a1 = a[1], c0 = ac[0];
     geo = a0.x != 0.f || a0.y != 0.f || a0.z != 0.f || a0.w != 0.f || a1.x != 0.f || a1.y != 0.f;
-    col = a1.z != 0.f || a1.w != 0.f || a2.x != 0.f;
-    if (geo || col) {
-      const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
+    col = c0.x != 0.f || c0.y != 0.f || c0.z != 0.f;
+    const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (geo) {  // leave the accumulators cleared for the next backward pass
       a[0] = zero4;
       a[1] = zero4;
-      a[2] = zero4;
-    }
-    if (geo) {
       float mu[3], Sig[9];
       geom_body(prm, i, mu, Sig);
       geom_view(mu, Sig, vt.v[0], a0, a1, g_mu, Gs, g_op);
     }
     if (col) {
+      ac[0] = zero4;
       const uint32_t mask = clampm[i];
-      gr[0] = (mask & 1u) ? 0.f : a1.z;
-      gr[1] = (mask & 2u) ? 0.f : a1.w;
-      gr[2] = (mask & 4u) ? 0.f : a2.x;
+      gr[0] = (mask & 1u) ? 0.f : c0.x;
+      gr[1] = (mask & 2u) ? 0.f : c0.y;
+      gr[2] = (mask & 4u) ? 0.f : c0.z;
     }
   }
   // colour: dL/dsh[j][c] = Y_j gr[c]; direction term into the mean gradient
@@ -575,8 +574,7 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd_one(ParamsDev prm, ViewT
 // view's colour gradient in c.
 template <int DEG, int kShViews>
 __global__ __launch_bounds__(256) void k_preprocess_bwd_sh(ParamsDev prm, ViewTable vt,
-                                                           float* __restrict__ acc,
-                                                           const uint2* __restrict__ rect,
+                                                           float* __restrict__ accC,
                                                            const uint8_t* __restrict__ clampm,
                                                            GradsDev gout) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -600,26 +598,18 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd_sh(ParamsDev prm, ViewTa
       inv[c] = 0.f;
       const int v = v0 + c;
       if (v < vt.n) {
+        // untouched entries, and touched ones without gradient, are zero
         const size_t o = (size_t)v * n + i;
-        const uint2 rc = rect[o];
-        if ((rc.y & 0xffffu) >= (rc.x & 0xffffu)) {  // touched in this view
-          float4* a = reinterpret_cast<float4*>(acc + o * kAccStride);
-          const float4 a0 = a[0], a1 = a[1], a2 = a[2];
-          const bool geo = a0.x != 0.f || a0.y != 0.f || a0.z != 0.f || a0.w != 0.f ||
-                           a1.x != 0.f || a1.y != 0.f;
-          const bool col = a1.z != 0.f || a1.w != 0.f || a2.x != 0.f;
-          if (geo || col) {
-            // leave the accumulator cleared for the next backward pass
-            const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
-            a[0] = zero4;
-            a[1] = zero4;
-            a[2] = zero4;
-          }
+        {
+          float4* a = reinterpret_cast<float4*>(accC + o * kAccC);
+          const float4 a0 = a[0];
+          const bool col = a0.x != 0.f || a0.y != 0.f || a0.z != 0.f;
           if (col) {
+            a[0] = make_float4(0.f, 0.f, 0.f, 0.f);  // cleared for the next backward pass
             const uint32_t mask = clampm[o];
-            gr[c][0] = (mask & 1u) ? 0.f : a1.z;
-            gr[c][1] = (mask & 2u) ? 0.f : a1.w;
-            gr[c][2] = (mask & 4u) ? 0.f : a2.x;
+            gr[c][0] = (mask & 1u) ? 0.f : a0.x;
+            gr[c][1] = (mask & 2u) ? 0.f : a0.y;
+            gr[c][2] = (mask & 4u) ? 0.f : a0.z;
             if (!mf_loaded) {
               for (int k = 0; k < 3; ++k) mf[k] = prm.means[k * n + i];
               mf_loaded = true;
@@ -720,24 +710,26 @@ gs_status launch_preprocess_fwd(const ParamsDev& p, const ViewTable& vt, Frame& 
 gs_status launch_preprocess_bwd(const ParamsDev& p, const ViewTable& vt, Frame& f,
                                 const GradsDev& g, hipStream_t s) {
   const int blocks = (int)((p.n + 255) / 256);
-  auto* ac = (float*)f.acc.p;
-  auto* rc = (const uint2*)f.rect.p;
+  auto* accG = (float*)f.acc.p;
+  auto* accC = accG + (size_t)f.views * (size_t)f.n * kAccG;
   auto* cm = (const uint8_t*)f.clampm.p;
-  auto go = [&](auto kern) {
-    hipLaunchKernelGGL(kern, dim3(blocks), dim3(256), 0, s, p, vt, ac, rc, cm, g);
-  };
   if (vt.n == 1) {
+    auto one = [&](auto kern) {
+      hipLaunchKernelGGL(kern, dim3(blocks), dim3(256), 0, s, p, vt, accG, accC, cm, g);
+    };
     switch (p.sh_degree) {
-      case 0: go(k_preprocess_bwd_one<0>); break;
-      case 1: go(k_preprocess_bwd_one<1>); break;
-      case 2: go(k_preprocess_bwd_one<2>); break;
-      default: go(k_preprocess_bwd_one<3>); break;
+      case 0: one(k_preprocess_bwd_one<0>); break;
+      case 1: one(k_preprocess_bwd_one<1>); break;
+      case 2: one(k_preprocess_bwd_one<2>); break;
+      default: one(k_preprocess_bwd_one<3>); break;
     }
     GS_LAUNCHED("preprocess_bwd_one");
     return GS_OK;
   }
-  hipLaunchKernelGGL(k_preprocess_bwd_geom, dim3(blocks), dim3(256), 0, s, p, vt,
-                     (const float*)ac, rc, g);
+  auto go = [&](auto kern) {
+    hipLaunchKernelGGL(kern, dim3(blocks), dim3(256), 0, s, p, vt, accC, cm, g);
+  };
+  hipLaunchKernelGGL(k_preprocess_bwd_geom, dim3(blocks), dim3(256), 0, s, p, vt, accG, g);
   GS_LAUNCHED("preprocess_bwd_geom");
   switch (p.sh_degree) {
     case 0: go(k_preprocess_bwd_sh<0, 4>); break;

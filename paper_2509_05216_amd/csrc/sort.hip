@@ -321,14 +321,20 @@ __global__ void k_clamp_count(const uint64_t* __restrict__ total, uint32_t cap,
   if (t > cap) *overflow = 1u;
 }
 
-// Sort key of a tile for the longest-first work queue: 2^20 - 1 - min(length, 2^20 - 1).
+// Sort key of a tile for the longest-first work queue: 255 minus a log-scale
+// length class (16 classes per octave of length + 1, lengths up to 2^16 - 1
+// distinguished), so one 8-bit pass orders the tiles by length to within 1/16
+// of an octave, which is all the schedule needs.
 __global__ __launch_bounds__(256) void k_tile_len_keys(const uint2* __restrict__ ranges,
                                                        uint32_t tiles, uint32_t* __restrict__ key) {
   const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= tiles) return;
   const uint2 r = ranges[t];
-  const uint32_t len = r.y - r.x;
-  key[t] = 0xFFFFFu - (len < 0xFFFFFu ? len : 0xFFFFFu);
+  const uint32_t x = r.y - r.x + 1u;                      // >= 1
+  const uint32_t e = 31u - (uint32_t)__clz((int)x);       // floor(log2 x)
+  const uint32_t m = ((x << (31u - e)) >> 27) & 15u;      // next four bits after the leading one
+  const uint32_t cls = e * 16u + m;
+  key[t] = 255u - (cls < 255u ? cls : 255u);
 }
 
 __global__ __launch_bounds__(256) void k_export_keys(const uint32_t* __restrict__ tkey,
@@ -474,7 +480,7 @@ gs_status launch_tile_order(Frame& f, hipStream_t s) {
   gs_status st = sort_pairs_u32(f.ctx, f.ss, (const uint32_t*)f.okey[1].p, nullptr,
                                 (uint32_t*)f.okey[0].p, (uint32_t*)f.oval[0].p,
                                 (uint32_t*)f.okey[1].p, (uint32_t*)f.oval[1].p, tiles, nullptr,
-                                20, &in_b, s);
+                                8, &in_b, s);
   if (st != GS_OK) return st;
   f.tile_order = (const uint32_t*)f.oval[in_b].p;
   return GS_OK;

@@ -11,9 +11,10 @@
 // adjoint) and combines them with the L1 term:
 //   dL/dx = s [(1 - lambda) sign(x - y) - lambda (w*g1 + 2 x w*g2 + y w*g3)],
 //   s = 1/(3 H W V).
-// Horizontal taps share w x between the moments and use explicit fused
-// multiply-adds; in the vertical pass each thread produces four consecutive
-// rows of one column from 14 LDS rows.  Loss sums are reduced per block into
+// A horizontal task makes four outputs of one halo row from 14 inputs (read
+// 8 bytes at a time, with x^2, y^2 and x y formed once per input), each tap an
+// explicit fused multiply-add per moment.  In the vertical pass each thread
+// produces four consecutive rows of one column from 14 LDS rows.  Loss sums are reduced per block into
 // float64 partials and summed by a final single-block kernel, so the loss
 // value is deterministic.
 #include "internal.h"
@@ -24,10 +25,11 @@ namespace {
 constexpr int kT = 32;           // output tile side
 constexpr int kR = 5;            // window radius
 constexpr int kN = 2 * kR + 1;   // taps
-constexpr int kH = kT + 2 * kR;  // 42: halo tile side
-constexpr int kP = kH + 1;       // padded LDS row of the halo tile
-constexpr int kQ = kT + 1;       // padded LDS row of the horizontal pass
+constexpr int kH = kT + 2 * kR;  // 42: halo tile side (LDS rows of 168 bytes, 8-byte aligned)
+constexpr int kQ = kT + 4;       // 36: LDS row of the horizontal pass (16-byte aligned)
 constexpr int kRows = 4;         // output rows per thread in the vertical pass
+constexpr int kGroups = kT / 4;  // four-wide output groups per row in the horizontal pass
+constexpr int kHTasks = kH * kGroups;  // 336 horizontal tasks (halo row, group)
 constexpr float kC1 = 0.01f * 0.01f;
 constexpr float kC2 = 0.03f * 0.03f;
 
@@ -35,19 +37,91 @@ struct Win {
   float w[kN];
 };
 
-constexpr int kLoads = (kH * kH + 255) / 256;  // halo elements per thread
+// Halo tiles are loaded by rows: wave w takes rows w, w + 4, ..., lane l
+// column l (lanes 42-63 load a valid clamped address and store nothing), so
+// the column clamp is a per-lane constant and the row clamp a scalar.
+constexpr int kHaloRows = (kH + 3) / 4;  // 11 rows per wave
 
-// Halo element t of the tile whose top-left halo pixel is (ox, oy): whether it
-// lies in the image, and an in-image offset to read (clamped, so every load is
-// valid; the value is replaced by zero padding when outside).
-__device__ inline bool halo_inside(int t, int ox, int oy, int W, int H) {
-  const int gx = ox + t % kH, gy = oy + t / kH;
-  return gx >= 0 && gx < W && gy >= 0 && gy < H;
+struct HaloCols {
+  uint32_t gxc;  // clamped image column of this lane
+  bool inx;      // lane < 42 and its column inside the image
+};
+
+__device__ inline HaloCols halo_cols(int ox, int W) {
+  const int lane = (int)(threadIdx.x % 64);
+  const int gx = ox + lane;
+  return {(uint32_t)min(max(gx, 0), W - 1), lane < kH && gx >= 0 && gx < W};
 }
 
-__device__ inline size_t halo_offset(int t, int ox, int oy, int W, int H) {
-  const int gx = min(max(ox + t % kH, 0), W - 1), gy = min(max(oy + t / kH, 0), H - 1);
-  return (size_t)gy * W + gx;
+// This thread's share of a halo tile of NI image planes (top-left halo pixel
+// row oy), into registers; the loads are issued together.
+template <int NI>
+__device__ inline void halo_load(const float* const (&img)[NI], HaloCols hc, int oy, int W, int H,
+                                 float (&v)[NI][kHaloRows]) {
+  // wave-uniform (scalar) row arithmetic; per lane only the column offset
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / 64));
+#pragma unroll
+  for (int k = 0; k < kHaloRows; ++k) {
+    const int gy = min(max(oy + wave + 4 * k, 0), H - 1);
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+      const float* rp = img[i] + (size_t)gy * W;
+      v[i][k] = rp[hc.gxc];
+    }
+  }
+  // keep every load here, ahead of the (predicated) stores, so that their
+  // latencies overlap instead of each store waiting for its own load
+#pragma unroll
+  for (int k = 0; k < kHaloRows; ++k)
+#pragma unroll
+    for (int i = 0; i < NI; ++i) asm volatile("" : "+v"(v[i][k]));
+}
+
+// ... and from registers into LDS tiles, zero outside the image.
+template <int NI>
+__device__ inline void halo_store(float (*const (&tile)[NI])[kH], const float (&v)[NI][kHaloRows],
+                                  HaloCols hc, int oy, int H) {
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / 64));
+  const int lane = (int)(threadIdx.x % 64);
+#pragma unroll
+  for (int k = 0; k < kHaloRows; ++k) {
+    const int r = wave + 4 * k;
+    const bool in = hc.inx && oy + r >= 0 && oy + r < H;
+    if (lane < kH && r < kH) {
+#pragma unroll
+      for (int i = 0; i < NI; ++i) tile[i][r][lane] = in ? v[i][k] : 0.f;
+    }
+  }
+}
+
+// Columns c0 .. c0 + 13 of row r of an LDS halo tile (c0 a multiple of 4, so
+// the seven 8-byte reads are aligned): the inputs of four horizontal outputs.
+__device__ inline void row14(const float (*tile)[kH], int r, int c0, float (&v)[14]) {
+  const float2* p = reinterpret_cast<const float2*>(&tile[r][c0]);
+#pragma unroll
+  for (int k = 0; k < 7; ++k) {
+    const float2 u = p[k];
+    v[2 * k] = u.x;
+    v[2 * k + 1] = u.y;
+  }
+}
+
+// Tile (bx, by) and channel bz of this block.  Workgroups are dispatched to
+// the eight XCDs (each with its own L2) in turn, so consecutive block indices
+// go to different XCDs; the permutation below gives each XCD a contiguous run
+// of tiles instead, so that the halos neighbouring tiles share are read into
+// the same L2.  A bijection (the last total % 8 blocks keep their place), so
+// every tile is done once whatever the dispatch order.
+__device__ inline void xcd_tile(int& bx, int& by, int& bz) {
+  const uint32_t gx = gridDim.x, gxy = gridDim.x * gridDim.y;
+  const uint32_t total = gxy * gridDim.z;
+  const uint32_t L = blockIdx.x + gx * (blockIdx.y + gridDim.y * blockIdx.z);
+  const uint32_t n8 = total / 8;
+  const uint32_t T = L < 8 * n8 ? (L % 8) * n8 + L / 8 : L;
+  bz = (int)(T / gxy);
+  const uint32_t r = T % gxy;
+  by = (int)(r / gx);
+  bx = (int)(r % gx);
 }
 
 // Thread layout of the vertical pass: column c, rows r0 .. r0 + 3.
@@ -77,56 +151,62 @@ __device__ inline void vert_filter(const float (*hq)[kH][kQ], const Win& win, in
   }
 }
 
+// One block per 32 x 32 tile and channel.
 __global__ __launch_bounds__(256) void k_ssim_fwd(const float* __restrict__ x,
                                                   const float* __restrict__ y, int W, int H,
                                                   Win win, float* __restrict__ gmap,
                                                   double* __restrict__ part) {
-  __shared__ float sx[kH][kP], sy[kH][kP];
-  __shared__ float hq[5][kH][kQ];
-  const int ch = blockIdx.z;
+  __shared__ alignas(16) float sx[kH][kH];
+  __shared__ alignas(16) float sy[kH][kH];
+  __shared__ alignas(16) float hq[5][kH][kQ];
+  int bx, by, ch;
+  xcd_tile(bx, by, ch);
   const size_t plane = (size_t)W * H;
-  const float* xc = x + ch * plane;
-  const float* yc = y + ch * plane;
-  const int ox = blockIdx.x * kT - kR, oy = blockIdx.y * kT - kR;
+  const int ox = bx * kT - kR, oy = by * kT - kR;
   {
     // every halo load is issued before the first LDS store (clamped addresses,
     // zero outside the image), so their latencies overlap
-    float vx[kLoads], vy[kLoads];
-#pragma unroll
-    for (int q = 0; q < kLoads; ++q) {
-      const size_t o = halo_offset(threadIdx.x + q * 256, ox, oy, W, H);
-      vx[q] = xc[o];
-      vy[q] = yc[o];
-    }
-#pragma unroll
-    for (int q = 0; q < kLoads; ++q) {
-      const int t = threadIdx.x + q * 256;
-      if (t < kH * kH) {
-        const bool in = halo_inside(t, ox, oy, W, H);
-        sx[t / kH][t % kH] = in ? vx[q] : 0.f;
-        sy[t / kH][t % kH] = in ? vy[q] : 0.f;
-      }
-    }
+    const HaloCols hc = halo_cols(ox, W);
+    const float* const src[2] = {x + ch * plane, y + ch * plane};
+    float (*const dst[2])[kH] = {sx, sy};
+    float v[2][kHaloRows];
+    halo_load<2>(src, hc, oy, W, H, v);
+    halo_store<2>(dst, v, hc, oy, H);
   }
   __syncthreads();
-  for (int t = threadIdx.x; t < kH * kT; t += 256) {
-    const int r = t / kT, c = t % kT;
-    float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f, a4 = 0.f;
+  // horizontal pass: four outputs of one halo row per task; the products x^2,
+  // y^2, x y are formed once per input, so each tap is five fused multiply-adds
+  for (int t = threadIdx.x; t < kHTasks; t += 256) {
+    const int r = t / kGroups, c0 = (t % kGroups) * 4;
+    float xv[14], yv[14];
+    row14(sx, r, c0, xv);
+    row14(sy, r, c0, yv);
+    float xx[14], yy[14], xy[14];
 #pragma unroll
-    for (int i = 0; i < kN; ++i) {
-      const float xv = sx[r][c + i], yv = sy[r][c + i];
-      const float wx = win.w[i] * xv, wy = win.w[i] * yv;
-      a0 += wx;
-      a1 += wy;
-      a2 = fmaf(wx, xv, a2);
-      a3 = fmaf(wy, yv, a3);
-      a4 = fmaf(wx, yv, a4);
+    for (int k = 0; k < 14; ++k) {
+      xx[k] = xv[k] * xv[k];
+      yy[k] = yv[k] * yv[k];
+      xy[k] = xv[k] * yv[k];
     }
-    hq[0][r][c] = a0;
-    hq[1][r][c] = a1;
-    hq[2][r][c] = a2;
-    hq[3][r][c] = a3;
-    hq[4][r][c] = a4;
+    float a0[4], a1[4], a2[4], a3[4], a4[4];
+#pragma unroll
+    for (int o = 0; o < 4; ++o) a0[o] = a1[o] = a2[o] = a3[o] = a4[o] = 0.f;
+#pragma unroll
+    for (int i = 0; i < kN; ++i)
+#pragma unroll
+      for (int o = 0; o < 4; ++o) {
+        const float w = win.w[i];
+        a0[o] = fmaf(w, xv[o + i], a0[o]);
+        a1[o] = fmaf(w, yv[o + i], a1[o]);
+        a2[o] = fmaf(w, xx[o + i], a2[o]);
+        a3[o] = fmaf(w, yy[o + i], a3[o]);
+        a4[o] = fmaf(w, xy[o + i], a4[o]);
+      }
+    *reinterpret_cast<float4*>(&hq[0][r][c0]) = make_float4(a0[0], a0[1], a0[2], a0[3]);
+    *reinterpret_cast<float4*>(&hq[1][r][c0]) = make_float4(a1[0], a1[1], a1[2], a1[3]);
+    *reinterpret_cast<float4*>(&hq[2][r][c0]) = make_float4(a2[0], a2[1], a2[2], a2[3]);
+    *reinterpret_cast<float4*>(&hq[3][r][c0]) = make_float4(a3[0], a3[1], a3[2], a3[3]);
+    *reinterpret_cast<float4*>(&hq[4][r][c0]) = make_float4(a4[0], a4[1], a4[2], a4[3]);
   }
   __syncthreads();
   int c, r0;
@@ -134,10 +214,10 @@ __global__ __launch_bounds__(256) void k_ssim_fwd(const float* __restrict__ x,
   float mom[kRows][5];
   vert_filter<5>(hq, win, c, r0, mom);
   double l1 = 0.0, ss = 0.0;
-  const int gx = blockIdx.x * kT + c;
+  const int gx = bx * kT + c;
 #pragma unroll
   for (int o = 0; o < kRows; ++o) {
-    const int gy = blockIdx.y * kT + r0 + o;
+    const int gy = by * kT + r0 + o;
     if (gx < W && gy < H) {
       const float mx = mom[o][0], my = mom[o][1];
       const float sxx = mom[o][2] - mx * mx, syy = mom[o][3] - my * my;
@@ -176,7 +256,7 @@ __global__ __launch_bounds__(256) void k_ssim_fwd(const float* __restrict__ x,
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    const size_t b = ((size_t)ch * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+    const size_t b = ((size_t)ch * gridDim.y + by) * gridDim.x + bx;
     part[2 * b + 0] = red[0][0] + red[0][1] + red[0][2] + red[0][3];
     part[2 * b + 1] = red[1][0] + red[1][1] + red[1][2] + red[1][3];
   }
@@ -187,54 +267,47 @@ __global__ __launch_bounds__(256) void k_ssim_bwd(const float* __restrict__ x,
                                                   Win win, const float* __restrict__ gmap,
                                                   float lambda, float scale,
                                                   float* __restrict__ dl) {
-  __shared__ float sg[3][kH][kP];
-  __shared__ float hq[3][kH][kQ];
-  const int ch = blockIdx.z;
+  __shared__ alignas(16) float sg[3][kH][kH];
+  __shared__ alignas(16) float hq[3][kH][kQ];
+  int bx, by, ch;
+  xcd_tile(bx, by, ch);
   const size_t plane = (size_t)W * H;
-  const int ox = blockIdx.x * kT - kR, oy = blockIdx.y * kT - kR;
+  const int ox = bx * kT - kR, oy = by * kT - kR;
   {
-    float v[3][kLoads];
-#pragma unroll
-    for (int q = 0; q < kLoads; ++q) {
-      const size_t o = halo_offset(threadIdx.x + q * 256, ox, oy, W, H);
-#pragma unroll
-      for (int m = 0; m < 3; ++m) v[m][q] = gmap[(m * 3 + ch) * plane + o];
-    }
-#pragma unroll
-    for (int q = 0; q < kLoads; ++q) {
-      const int t = threadIdx.x + q * 256;
-      if (t < kH * kH) {
-        const bool in = halo_inside(t, ox, oy, W, H);
-#pragma unroll
-        for (int m = 0; m < 3; ++m) sg[m][t / kH][t % kH] = in ? v[m][q] : 0.f;
-      }
-    }
+    const HaloCols hc = halo_cols(ox, W);
+    const float* const src[3] = {gmap + (size_t)(0 * 3 + ch) * plane,
+                                 gmap + (size_t)(1 * 3 + ch) * plane,
+                                 gmap + (size_t)(2 * 3 + ch) * plane};
+    float (*const dst[3])[kH] = {sg[0], sg[1], sg[2]};
+    float v[3][kHaloRows];
+    halo_load<3>(src, hc, oy, W, H, v);
+    halo_store<3>(dst, v, hc, oy, H);
   }
   __syncthreads();
-  for (int t = threadIdx.x; t < kH * kT; t += 256) {
-    const int r = t / kT, c = t % kT;
-    float a0 = 0.f, a1 = 0.f, a2 = 0.f;
+  for (int t = threadIdx.x; t < kHTasks; t += 256) {
+    const int r = t / kGroups, c0 = (t % kGroups) * 4;
 #pragma unroll
-    for (int i = 0; i < kN; ++i) {
-      const float w = win.w[i];
-      a0 = fmaf(w, sg[0][r][c + i], a0);
-      a1 = fmaf(w, sg[1][r][c + i], a1);
-      a2 = fmaf(w, sg[2][r][c + i], a2);
+    for (int m = 0; m < 3; ++m) {
+      float gv[14];
+      row14(sg[m], r, c0, gv);
+      float a[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int i = 0; i < kN; ++i)
+#pragma unroll
+        for (int o = 0; o < 4; ++o) a[o] = fmaf(win.w[i], gv[o + i], a[o]);
+      *reinterpret_cast<float4*>(&hq[m][r][c0]) = make_float4(a[0], a[1], a[2], a[3]);
     }
-    hq[0][r][c] = a0;
-    hq[1][r][c] = a1;
-    hq[2][r][c] = a2;
   }
   __syncthreads();
   int c, r0;
   vert_slot(c, r0);
   float f[kRows][3];
   vert_filter<3>(hq, win, c, r0, f);
-  const int gx = blockIdx.x * kT + c;
+  const int gx = bx * kT + c;
   if (gx >= W) return;
 #pragma unroll
   for (int o = 0; o < kRows; ++o) {
-    const int gy = blockIdx.y * kT + r0 + o;
+    const int gy = by * kT + r0 + o;
     if (gy >= H) break;
     const size_t pix = ch * plane + (size_t)gy * W + gx;
     const float xv = x[pix], yv = y[pix];

@@ -488,12 +488,13 @@ __device__ inline void bwd_tile(BwdSmem<TILE, DEPTH>& sm, const ViewTable& vt, i
   __syncthreads();
   uint32_t maxn = 0;
   for (int w = 0; w < NW; ++w) maxn = max(maxn, smax[w]);
+  // the sum table starts cleared; each flush clears the entries it consumed
+  for (int j = threadIdx.x; j < 9 * kPart; j += NT) part[j] = 0.f;
 
   for (int hi = (int)maxn; hi > 0; hi -= DEPTH) {
     const int lo = max(0, hi - DEPTH);
     const int cnt = hi - lo;
     __syncthreads();
-    for (int j = threadIdx.x; j < 9 * kPart; j += NT) part[j] = 0.f;
     stage_batch<TILE, DEPTH>(st, tval, splat, rg.x + (uint32_t)lo, cnt, tile_x * TILE,
                              tile_y * TILE);
     // walk this wave's overlapping slots from the back, below its last contributor
@@ -589,29 +590,35 @@ __device__ inline void bwd_tile(BwdSmem<TILE, DEPTH>& sm, const ViewTable& vt, i
       }
     }
     __syncthreads();
+    // flush, first the per-slot transforms (one thread per slot, in place):
+    // mean (A dx + B dy, B dx + C dy) dpow summed = the conic applied to the
+    // first two sums; conic -dpow dx^2 / 2, -dpow dx dy, -dpow dy^2 / 2;
+    // opacity: sum of dpow / o
+    if ((int)threadIdx.x < cnt) {
+      const int j = threadIdx.x;
+      const float4 q = st.s0[j];
+      const float A = q.x * (-2.f * kLn2), B = q.y * -kLn2, C = q.z * (-2.f * kLn2);
+      const float e0 = part[j], e1 = part[kPart + j];
+      part[j] = fmaf(A, e0, B * e1);
+      part[kPart + j] = fmaf(B, e0, C * e1);
+      part[2 * kPart + j] *= -0.5f;
+      part[3 * kPart + j] *= -1.f;
+      part[4 * kPart + j] *= -0.5f;
+      part[5 * kPart + j] *= __builtin_amdgcn_rcpf(q.w);  // o >= 1/255: 1-ulp reciprocal
+    }
+    __syncthreads();
+    // then the atomics, (slot, component) interleaved: the six geometric sums
+    // of a (view, Gaussian) share one 32-byte record and its colour sums one
+    // 16-byte record, so neighbouring lanes' atomics fall in few cache lines;
+    // each consumed entry is cleared for the next batch
     for (int t = threadIdx.x; t < cnt * 9; t += NT) {
       const int j = t / 9, c = t - j * 9;
-      float s = part[c * kPart + j];
-      if (c < 2) {
-        // mean: (A dx + B dy, B dx + C dy) dpow summed = conic applied to the sums
-        const float4 q = st.s0[j];
-        const float A = q.x * (-2.f * kLn2), B = q.y * -kLn2, C = q.z * (-2.f * kLn2);
-        const float e0 = part[j], e1 = part[kPart + j];
-        s = c == 0 ? fmaf(A, e0, B * e1) : fmaf(B, e0, C * e1);
-      } else if (c < 5) {
-        s *= c == 3 ? -1.f : -0.5f;  // conic: -dpow dx^2 / 2, -dpow dx dy, -dpow dy^2 / 2
-      } else if (c == 5) {
-        s = s / st.s0[j].w;  // opacity: sum of dpow / o
-      }
+      const float s = part[c * kPart + j];
+      part[c * kPart + j] = 0.f;
       if (s != 0.f) {
-        // record-major accumulators: the six geometric sums of a (view, Gaussian)
-        // share one 32-byte record and its colour sums one 16-byte record, so
-        // neighbouring lanes' atomics fall in few cache lines
         const size_t o = st.sidx[j];
-        if (c < 6)
-          atomicAdd(accG + o * kAccG + c, s);
-        else
-          atomicAdd(accC + o * kAccC + (c - 6), s);
+        float* const dst = c < 6 ? accG + o * kAccG + c : accC + o * kAccC + (c - 6);
+        atomicAdd(dst, s);
       }
     }
   }

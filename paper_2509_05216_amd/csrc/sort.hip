@@ -165,11 +165,29 @@ __global__ __launch_bounds__(kThreads) void k_radix_hist(const uint32_t* __restr
   for (int d = threadIdx.x; d < kWaves * kRadix; d += kThreads) (&h[0][0])[d] = 0;
   __syncthreads();
   const uint32_t n = load_n(n_max, d_n);
+  // the wave's 1024 keys as four 16-byte reads per lane, all issued before the
+  // counting (the order of counting does not matter)
   const uint32_t base = blockIdx.x * (uint32_t)kChunk + wave * 64 * kItems;
-#pragma unroll 4
-  for (int j = 0; j < kItems; ++j) {
-    const uint32_t i = base + j * 64 + lane;
-    if (i < n) atomicAdd(&h[wave][(keys[i] >> shift) & 0xffu], 1u);
+  uint4 q[kItems / 4];
+#pragma unroll
+  for (int j = 0; j < kItems / 4; ++j) {
+    const uint32_t i = base + 4u * (j * 64 + lane);
+    if (i + 4 <= n) {
+      q[j] = *reinterpret_cast<const uint4*>(keys + i);
+    } else {  // tail: absent keys marked ~0 and skipped below
+      q[j].x = i < n ? keys[i] : ~0u;
+      q[j].y = i + 1 < n ? keys[i + 1] : ~0u;
+      q[j].z = i + 2 < n ? keys[i + 2] : ~0u;
+      q[j].w = ~0u;
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < kItems / 4; ++j) {
+    const uint32_t i = base + 4u * (j * 64 + lane);
+    const uint32_t kk[4] = {q[j].x, q[j].y, q[j].z, q[j].w};
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (i + u < n) atomicAdd(&h[wave][(kk[u] >> shift) & 0xffu], 1u);
   }
   __syncthreads();
   for (int d = threadIdx.x; d < kRadix; d += kThreads) {
@@ -298,14 +316,33 @@ __global__ __launch_bounds__(256) void k_emit(ViewTable vt, int n_gauss,
     }
 }
 
+// Per-tile [start, end) of the sorted keys: four keys per thread (one 16-byte
+// read, plus the neighbours on either side); a run boundary sets the range.
 __global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ tkey, uint32_t K_max,
                                                 const uint32_t* d_K, uint2* __restrict__ ranges) {
-  const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t k0 = 4u * (blockIdx.x * blockDim.x + threadIdx.x);
   const uint32_t K = load_n(K_max, d_K);
-  if (k >= K) return;
-  const uint32_t t = tkey[k];
-  if (k == 0 || tkey[k - 1] != t) ranges[t].x = k;
-  if (k == K - 1 || tkey[k + 1] != t) ranges[t].y = k + 1;
+  if (k0 >= K) return;
+  uint32_t t[6];  // keys k0 - 1 .. k0 + 4 (~0 outside [0, K): differs from every tile)
+  t[0] = k0 > 0 ? tkey[k0 - 1] : ~0u;
+  if (k0 + 4 <= K) {
+    const uint4 q = *reinterpret_cast<const uint4*>(tkey + k0);
+    t[1] = q.x;
+    t[2] = q.y;
+    t[3] = q.z;
+    t[4] = q.w;
+  } else {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) t[u + 1] = k0 + u < K ? tkey[k0 + u] : ~0u;
+  }
+  t[5] = k0 + 4 < K ? tkey[k0 + 4] : ~0u;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const uint32_t k = k0 + u;
+    if (k >= K) break;
+    if (t[u] != t[u + 1]) ranges[t[u + 1]].x = k;
+    if (t[u + 2] != t[u + 1]) ranges[t[u + 1]].y = k + 1;
+  }
 }
 
 __global__ __launch_bounds__(256) void k_fill_u32(uint32_t* p, uint32_t value, size_t count) {
@@ -445,7 +482,8 @@ gs_status launch_ranges(Frame& f, uint32_t n_rec, const uint32_t* d_K, hipStream
   gs_status st = launch_fill_u32(f.ranges.p, 0u, (size_t)f.vt.total_tiles * 2, s);
   if (st != GS_OK) return st;
   if (n_rec == 0) return GS_OK;
-  hipLaunchKernelGGL(k_ranges, dim3((n_rec + 255) / 256), dim3(256), 0, s,
+  const uint32_t quads = (n_rec + 3) / 4;
+  hipLaunchKernelGGL(k_ranges, dim3((quads + 255) / 256), dim3(256), 0, s,
                      (const uint32_t*)f.tkey[f.tkey_sel].p, n_rec, d_K, (uint2*)f.ranges.p);
   GS_LAUNCHED("ranges");
   return GS_OK;

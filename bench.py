@@ -41,12 +41,12 @@ FLOP_PAIR_BWD = 68
 MEASURED_TRAFFIC = [
     {"kernel": "blend_bwd", "views": 4, "tile": 16, "lds_depth": 256, "flags": 3,
      "source": "paper_2509_05216_amd/csrc/blend.hip",
-     "sha256": "b236a7eeb55dc03880d3d5ea60eebd765564d88da4ebbebe057e6d1270c50ee6",
-     "read_bytes": 3160.2e6, "write_bytes": 932.5e6},
+     "sha256": "7def0712b90e01e31e2b8096941e9259e24c3b6ddae0602cce76d6c17d6ebdde",
+     "read_bytes": 3192.4e6, "write_bytes": 935.5e6},
     {"kernel": "blend_bwd", "views": 4, "tile": 16, "lds_depth": 128, "flags": 3,
      "source": "paper_2509_05216_amd/csrc/blend.hip",
-     "sha256": "b236a7eeb55dc03880d3d5ea60eebd765564d88da4ebbebe057e6d1270c50ee6",
-     "read_bytes": 3139.8e6, "write_bytes": 932.5e6},
+     "sha256": "7def0712b90e01e31e2b8096941e9259e24c3b6ddae0602cce76d6c17d6ebdde",
+     "read_bytes": 3170.5e6, "write_bytes": 935.5e6},
 ]
 
 

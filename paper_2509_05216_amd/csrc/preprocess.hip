@@ -93,31 +93,42 @@ __device__ inline void sh_basis_grad_dot(float x, float y, float z, int deg, con
 }
 
 // View-independent 3-D state of one Gaussian.
-struct Body {
-  double mu[3];
-  double s[3];      // exp(log_scale)
-  double qn[4];     // normalised quaternion (w, x, y, z)
-  double qnorm;
-  double Rq[9];     // rotation, row-major
-  double Sig[9];    // 3-D covariance, row-major (symmetric)
+// Per-Gaussian state in precision F: float64 for the forward (its binning
+// decisions must be those of any float64 evaluation), float32 for the
+// backward, which takes no such decision.
+template <typename F>
+struct BodyT {
+  F mu[3];
+  F s[3];      // exp(log_scale)
+  F qn[4];     // normalised quaternion (w, x, y, z)
+  F qnorm;
+  F Rq[9];     // rotation, row-major
+  F Sig[9];    // 3-D covariance, row-major (symmetric)
 };
+using Body = BodyT<double>;
 
-__device__ inline void load_body(const ParamsDev& p, int i, Body& b) {
+template <typename F>
+__device__ inline void load_body(const ParamsDev& p, int i, BodyT<F>& b) {
   const int n = p.n;
   for (int k = 0; k < 3; ++k) {
-    b.mu[k] = (double)p.means[k * n + i];
-    b.s[k] = exp((double)p.log_scales[k * n + i]);
+    b.mu[k] = (F)p.means[k * n + i];
+    b.s[k] = exp((F)p.log_scales[k * n + i]);
   }
-  double q[4];
-  for (int k = 0; k < 4; ++k) q[k] = (double)p.quats[k * n + i];
+  F q[4];
+  for (int k = 0; k < 4; ++k) q[k] = (F)p.quats[k * n + i];
   b.qnorm = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
-  for (int k = 0; k < 4; ++k) b.qn[k] = q[k] / b.qnorm;
-  const double w = b.qn[0], x = b.qn[1], y = b.qn[2], z = b.qn[3];
-  double* R = b.Rq;
+  if constexpr (sizeof(F) == 8) {
+    for (int k = 0; k < 4; ++k) b.qn[k] = q[k] / b.qnorm;
+  } else {
+    const F iq = (F)1 / b.qnorm;
+    for (int k = 0; k < 4; ++k) b.qn[k] = q[k] * iq;
+  }
+  const F w = b.qn[0], x = b.qn[1], y = b.qn[2], z = b.qn[3];
+  F* R = b.Rq;
   R[0] = 1 - 2 * (y * y + z * z); R[1] = 2 * (x * y - w * z);     R[2] = 2 * (x * z + w * y);
   R[3] = 2 * (x * y + w * z);     R[4] = 1 - 2 * (x * x + z * z); R[5] = 2 * (y * z - w * x);
   R[6] = 2 * (x * z - w * y);     R[7] = 2 * (y * z + w * x);     R[8] = 1 - 2 * (x * x + y * y);
-  double M[9];
+  F M[9];
   for (int r = 0; r < 3; ++r)
     for (int c = 0; c < 3; ++c) M[r * 3 + c] = R[r * 3 + c] * b.s[c];
   for (int r = 0; r < 3; ++r)
@@ -373,54 +384,55 @@ __device__ inline void geom_view(const float* mu, const float* Sig, const CamDev
 }
 
 // Scale and rotation gradients from the summed dL/dSigma3, and the opacity
-// logit's from the summed opacity gradient (float64 body of Gaussian i).
+// logit's from the summed opacity gradient (float32 body of Gaussian i).
 __device__ inline void geom_finish(const ParamsDev& prm, int i, const float* Gs, float g_op,
                                    float* g_ls, float* g_q, float& g_logit) {
-  Body b;
+  BodyT<float> b;
   load_body(prm, i, b);
-  const double G[9] = {Gs[0], Gs[1], Gs[2], Gs[1], Gs[3], Gs[4], Gs[2], Gs[4], Gs[5]};
+  const float G[9] = {Gs[0], Gs[1], Gs[2], Gs[1], Gs[3], Gs[4], Gs[2], Gs[4], Gs[5]};
   // Sigma3 = M M^T, M = Rq diag(s)
-  double M[9];
+  float M[9];
   for (int r = 0; r < 3; ++r)
     for (int q = 0; q < 3; ++q) M[r * 3 + q] = b.Rq[r * 3 + q] * b.s[q];
-  double gM[9];
+  float gM[9];
   for (int r = 0; r < 3; ++r)
     for (int q = 0; q < 3; ++q)
       gM[r * 3 + q] = G[r * 3 + 0] * M[0 * 3 + q] + G[r * 3 + 1] * M[1 * 3 + q] +
                       G[r * 3 + 2] * M[2 * 3 + q];
-  double gR[9];
+  float gR[9];
   for (int r = 0; r < 3; ++r)
     for (int q = 0; q < 3; ++q) gR[r * 3 + q] = gM[r * 3 + q] * b.s[q];
   for (int q = 0; q < 3; ++q) {
-    const double gsq = gM[0 * 3 + q] * b.Rq[0 * 3 + q] + gM[1 * 3 + q] * b.Rq[1 * 3 + q] +
-                       gM[2 * 3 + q] * b.Rq[2 * 3 + q];
-    g_ls[q] = (float)(gsq * b.s[q]);
+    const float gsq = gM[0 * 3 + q] * b.Rq[0 * 3 + q] + gM[1 * 3 + q] * b.Rq[1 * 3 + q] +
+                      gM[2 * 3 + q] * b.Rq[2 * 3 + q];
+    g_ls[q] = gsq * b.s[q];
   }
   // rotation of the unit quaternion, entry by entry
-  const double w = b.qn[0], x = b.qn[1], y = b.qn[2], z = b.qn[3];
-  const double* g = gR;
-  const double gw = 2 * (-z * g[1] + y * g[2] + z * g[3] - x * g[5] - y * g[6] + x * g[7]);
-  const double gx = 2 * (y * g[1] + z * g[2] + y * g[3] - 2 * x * g[4] - w * g[5] + z * g[6] +
-                         w * g[7] - 2 * x * g[8]);
-  const double gy = 2 * (-2 * y * g[0] + x * g[1] + w * g[2] + x * g[3] + z * g[5] - w * g[6] +
-                         z * g[7] - 2 * y * g[8]);
-  const double gz = 2 * (-2 * z * g[0] - w * g[1] + x * g[2] + w * g[3] - 2 * z * g[4] +
-                         y * g[5] + x * g[6] + y * g[7]);
-  const double dot = w * gw + x * gx + y * gy + z * gz;
-  g_q[0] = (float)((gw - w * dot) / b.qnorm);
-  g_q[1] = (float)((gx - x * dot) / b.qnorm);
-  g_q[2] = (float)((gy - y * dot) / b.qnorm);
-  g_q[3] = (float)((gz - z * dot) / b.qnorm);
-  const double op = 1.0 / (1.0 + exp(-(double)prm.logits[i]));
-  g_logit = (float)(g_op * op * (1.0 - op));
+  const float w = b.qn[0], x = b.qn[1], y = b.qn[2], z = b.qn[3];
+  const float* g = gR;
+  const float gw = 2 * (-z * g[1] + y * g[2] + z * g[3] - x * g[5] - y * g[6] + x * g[7]);
+  const float gx = 2 * (y * g[1] + z * g[2] + y * g[3] - 2 * x * g[4] - w * g[5] + z * g[6] +
+                        w * g[7] - 2 * x * g[8]);
+  const float gy = 2 * (-2 * y * g[0] + x * g[1] + w * g[2] + x * g[3] + z * g[5] - w * g[6] +
+                        z * g[7] - 2 * y * g[8]);
+  const float gz = 2 * (-2 * z * g[0] - w * g[1] + x * g[2] + w * g[3] - 2 * z * g[4] +
+                        y * g[5] + x * g[6] + y * g[7]);
+  const float dot = w * gw + x * gx + y * gy + z * gz;
+  const float iq = 1.f / b.qnorm;
+  g_q[0] = (gw - w * dot) * iq;
+  g_q[1] = (gx - x * dot) * iq;
+  g_q[2] = (gy - y * dot) * iq;
+  g_q[3] = (gz - z * dot) * iq;
+  const float op = 1.f / (1.f + expf(-prm.logits[i]));
+  g_logit = g_op * op * (1.f - op);
 }
 
 // Mean, Sigma3 (float32) of Gaussian i.
 __device__ inline void geom_body(const ParamsDev& prm, int i, float* mu, float* Sig) {
-  Body b;
+  BodyT<float> b;
   load_body(prm, i, b);
-  for (int k = 0; k < 3; ++k) mu[k] = (float)b.mu[k];
-  for (int k = 0; k < 9; ++k) Sig[k] = (float)b.Sig[k];
+  for (int k = 0; k < 3; ++k) mu[k] = b.mu[k];
+  for (int k = 0; k < 9; ++k) Sig[k] = b.Sig[k];
 }
 
 __global__ __launch_bounds__(256) void k_preprocess_bwd_geom(ParamsDev prm, ViewTable vt,

@@ -285,6 +285,13 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(
 }
 
 // ---------------------------------------------------------------- emission
+// Records of every (view, Gaussian) entry in depth order: (global tile, entry)
+// for each tile of its rectangle, row by row.  A wave writes its 64 entries'
+// records together: lane r of a pass takes the wave's record r (the owning
+// entry found by a search over the wave's prefix sums of record counts), so
+// each pass stores 64 consecutive records and no lane idles behind a large
+// rectangle.  An entry whose records would pass the capacity writes none and
+// sets the overflow word.
 __global__ __launch_bounds__(256) void k_emit(ViewTable vt, int n_gauss,
                                               const uint32_t* __restrict__ sidx,
                                               const uint32_t* __restrict__ srx,
@@ -294,26 +301,60 @@ __global__ __launch_bounds__(256) void k_emit(ViewTable vt, int n_gauss,
                                               uint32_t* __restrict__ tval,
                                               uint32_t* overflow) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= count) return;
-  const uint32_t idx = sidx[i];
-  const uint2 r = make_uint2(srx[i], sry[i]);  // rect[idx], gathered in depth order by k_counts
-  const int x0 = (int)(r.x & 0xffffu), y0 = (int)(r.x >> 16);
-  const int x1 = (int)(r.y & 0xffffu), y1 = (int)(r.y >> 16);
-  if (x1 < x0 || y1 < y0) return;
-  const int v = (int)(idx / (uint32_t)n_gauss);
-  const int tx = vt.v[v].tiles_x, toff = vt.v[v].tile_offset;
-  uint32_t o = offs[i];
-  const uint32_t need = (uint32_t)((x1 - x0 + 1) * (y1 - y0 + 1));
-  if ((uint64_t)o + need > cap) {
-    if (overflow != nullptr) *overflow = 1u;
-    return;
-  }
-  for (int y = y0; y <= y1; ++y)
-    for (int x = x0; x <= x1; ++x) {
-      tkey[o] = (uint32_t)(toff + y * tx + x);
-      tval[o] = idx;
-      ++o;
+  const int lane = __lane_id();
+  uint32_t need = 0, o = 0, idx = 0, key0 = 0, w = 1, tx = 0;
+  if (i < count) {
+    idx = sidx[i];
+    const uint2 r = make_uint2(srx[i], sry[i]);  // rect[idx], gathered in depth order by k_counts
+    const int x0 = (int)(r.x & 0xffffu), y0 = (int)(r.x >> 16);
+    const int x1 = (int)(r.y & 0xffffu), y1 = (int)(r.y >> 16);
+    if (x1 >= x0 && y1 >= y0) {
+      const int v = (int)(idx / (uint32_t)n_gauss);
+      tx = (uint32_t)vt.v[v].tiles_x;
+      o = offs[i];
+      const uint32_t nd = (uint32_t)((x1 - x0 + 1) * (y1 - y0 + 1));
+      if ((uint64_t)o + nd > cap) {
+        if (overflow != nullptr) *overflow = 1u;
+      } else {
+        need = nd;
+        w = (uint32_t)(x1 - x0 + 1);
+        key0 = (uint32_t)vt.v[v].tile_offset + (uint32_t)y0 * tx + (uint32_t)x0;
+      }
     }
+  }
+  // exclusive prefix of the record counts over the wave, and the wave total
+  uint32_t incl = need;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t t = (uint32_t)__shfl_up((int)incl, d, 64);
+    if (lane >= d) incl += t;
+  }
+  const uint32_t excl = incl - need;
+  const uint32_t total = (uint32_t)__shfl((int)incl, 63, 64);
+  // wave-uniform passes (every lane takes part in the shuffles)
+  for (uint32_t base = 0; base < total; base += 64) {
+    const uint32_t rr = base + (uint32_t)lane;
+    const bool act = rr < total;
+    // owner: the largest lane l with excl_l <= rr (never a lane without records)
+    int l = 0;
+#pragma unroll
+    for (int step = 32; step >= 1; step >>= 1) {
+      const int c = l + step;
+      const uint32_t e = (uint32_t)__shfl((int)excl, c, 64);
+      if (e <= rr) l = c;
+    }
+    const uint32_t li = rr - (uint32_t)__shfl((int)excl, l, 64);
+    const uint32_t wl = (uint32_t)__shfl((int)w, l, 64);
+    const uint32_t txl = (uint32_t)__shfl((int)tx, l, 64);
+    const uint32_t k0 = (uint32_t)__shfl((int)key0, l, 64);
+    const uint32_t ol = (uint32_t)__shfl((int)o, l, 64);
+    const uint32_t il = (uint32_t)__shfl((int)idx, l, 64);
+    if (act) {
+      const uint32_t yy = li / wl, xx = li - yy * wl;
+      tkey[ol + li] = k0 + yy * txl + xx;
+      tval[ol + li] = il;
+    }
+  }
 }
 
 // Per-tile [start, end) of the sorted keys: four keys per thread (one 16-byte

@@ -232,12 +232,19 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(
     const uint32_t i = base + j * 64 + lane;
     const bool ok = i < n;
     const uint32_t d = (key[j] >> shift) & 0xffu;
-    uint64_t peers = __ballot(ok);
+    // lanes with the same digit: for every bit, the ballot of the bit where the
+    // lane's bit is set, its complement where it is clear, on the two 32-bit
+    // halves (sbit: the bit sign-extended, 0 or all ones)
+    const uint64_t okm = __builtin_amdgcn_ballot_w64(ok);
+    uint32_t plo = (uint32_t)okm, phi = (uint32_t)(okm >> 32);
 #pragma unroll
     for (int b = 0; b < 8; ++b) {
-      const uint64_t bb = __ballot((d >> b) & 1u);
-      peers &= ((d >> b) & 1u) ? bb : ~bb;
+      const int32_t sbit = (int32_t)(d << (31 - b)) >> 31;
+      const uint64_t bb = __builtin_amdgcn_ballot_w64(sbit != 0);
+      plo &= ~((uint32_t)bb ^ (uint32_t)sbit);
+      phi &= ~((uint32_t)(bb >> 32) ^ (uint32_t)sbit);
     }
+    const uint64_t peers = ((uint64_t)phi << 32) | plo;
     uint32_t old = 0;
     const int leader = 63 - __clzll((long long)peers);
     if (ok && lane == leader) {

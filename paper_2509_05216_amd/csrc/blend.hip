@@ -237,12 +237,14 @@ __device__ inline void fwd_tile(Stage<TILE * TILE, DEPTH>& st, const ViewTable& 
       const float alpha = fminf(kAlphaMax, s.q0.w * __builtin_amdgcn_exp2f(p2));
       uint64_t m_use = ~done_m & __builtin_amdgcn_ballot_w64(!(p2 > 0.f)) &
                        __builtin_amdgcn_ballot_w64(!(alpha < kAlphaMin));
-      const float Tn = T * (1.f - alpha);
+      // weight alpha T and the transmittance after, T - alpha T = T (1 - alpha)
+      const float wa = alpha * T;
+      const float Tn = T - wa;
       const uint64_t m_stop = m_use & __builtin_amdgcn_ballot_w64(Tn < kTMin);
       done_m |= m_stop;
       m_use &= ~m_stop;
       const bool use = __builtin_amdgcn_inverse_ballot_w64(m_use);
-      const float w = use ? alpha * T : 0.f;
+      const float w = use ? wa : 0.f;
       cr = fmaf(s.q2.x, w, cr);
       cg = fmaf(s.q2.y, w, cg);
       cb = fmaf(s.q2.z, w, cb);

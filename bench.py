@@ -41,12 +41,12 @@ FLOP_PAIR_BWD = 68
 MEASURED_TRAFFIC = [
     {"kernel": "blend_bwd", "views": 4, "tile": 16, "lds_depth": 256, "flags": 3,
      "source": "paper_2509_05216_amd/csrc/blend.hip",
-     "sha256": "7def0712b90e01e31e2b8096941e9259e24c3b6ddae0602cce76d6c17d6ebdde",
-     "read_bytes": 3192.4e6, "write_bytes": 935.5e6},
+     "sha256": "6e1c20d66f1a0900399d0c1d3214859b144c1fa05b127dffbdde43c209fc4505",
+     "read_bytes": 3193.1e6, "write_bytes": 935.5e6},
     {"kernel": "blend_bwd", "views": 4, "tile": 16, "lds_depth": 128, "flags": 3,
      "source": "paper_2509_05216_amd/csrc/blend.hip",
-     "sha256": "7def0712b90e01e31e2b8096941e9259e24c3b6ddae0602cce76d6c17d6ebdde",
-     "read_bytes": 3170.5e6, "write_bytes": 935.5e6},
+     "sha256": "6e1c20d66f1a0900399d0c1d3214859b144c1fa05b127dffbdde43c209fc4505",
+     "read_bytes": 3171.0e6, "write_bytes": 935.5e6},
 ]
 
 

@@ -165,16 +165,32 @@ __device__ inline void view_cov(const R* mu, const R* Sig, const CamDev& c, Proj
   p.visible = p.t[2] > (R)c.znear;
   const R tz = p.visible ? p.t[2] : R(1);
   const R fx = (R)c.fx, fy = (R)c.fy;
-  p.limx = R(kGuard) * (R(0.5) * (R)c.W / fx);
-  p.limy = R(kGuard) * (R(0.5) * (R)c.H / fy);
-  p.xz = p.t[0] / tz;
-  p.yz = p.t[1] / tz;
-  p.u = fmin(fmax(p.xz, -p.limx), p.limx);
-  p.v = fmin(fmax(p.yz, -p.limy), p.limy);
-  p.J00 = fx / tz;
-  p.J02 = -fx * p.u / tz;
-  p.J11 = fy / tz;
-  p.J12 = -fy * p.v / tz;
+  if constexpr (sizeof(R) == 8) {
+    // float64: the divisions of the definition (binning decisions follow them)
+    p.limx = R(kGuard) * (R(0.5) * (R)c.W / fx);
+    p.limy = R(kGuard) * (R(0.5) * (R)c.H / fy);
+    p.xz = p.t[0] / tz;
+    p.yz = p.t[1] / tz;
+    p.u = fmin(fmax(p.xz, -p.limx), p.limx);
+    p.v = fmin(fmax(p.yz, -p.limy), p.limy);
+    p.J00 = fx / tz;
+    p.J02 = -fx * p.u / tz;
+    p.J11 = fy / tz;
+    p.J12 = -fy * p.v / tz;
+  } else {
+    // float32 (gradients only): one hardware reciprocal of t_z (1 ulp) and products
+    const R itz = __builtin_amdgcn_rcpf(tz);
+    p.limx = R(kGuard) * (R(0.5) * (R)c.W * __builtin_amdgcn_rcpf(fx));
+    p.limy = R(kGuard) * (R(0.5) * (R)c.H * __builtin_amdgcn_rcpf(fy));
+    p.xz = p.t[0] * itz;
+    p.yz = p.t[1] * itz;
+    p.u = fmin(fmax(p.xz, -p.limx), p.limx);
+    p.v = fmin(fmax(p.yz, -p.limy), p.limy);
+    p.J00 = fx * itz;
+    p.J02 = -fx * p.u * itz;
+    p.J11 = fy * itz;
+    p.J12 = -fy * p.v * itz;
+  }
   for (int j = 0; j < 3; ++j) {
     p.T0[j] = p.J00 * (R)Rc[0 * 3 + j] + p.J02 * (R)Rc[2 * 3 + j];
     p.T1[j] = p.J11 * (R)Rc[1 * 3 + j] + p.J12 * (R)Rc[2 * 3 + j];
@@ -328,8 +344,8 @@ __device__ inline void geom_view(const float* mu, const float* Sig, const CamDev
   view_cov(mu, Sig, c, p);
   const float gmx = a0.x, gmy = a0.y, gA = a0.z, gB = a0.w, gC = a1.x;
   g_op += a1.y;
-  // conic (A, B, C) = (c, -b, a) / det
-  const float iD = 1.f / p.det;
+  // conic (A, B, C) = (c, -b, a) / det (det >= 0.09: the low-pass)
+  const float iD = __builtin_amdgcn_rcpf(p.det);
   const float gD = -(gA * p.c - gB * p.b + gC * p.a) * iD * iD;
   const float ga = gC * iD + gD * p.c;
   const float gb = -gB * iD - 2.f * gD * p.b;
@@ -361,7 +377,7 @@ __device__ inline void geom_view(const float* mu, const float* Sig, const CamDev
   }
   const float tx = p.t[0], ty = p.t[1], tz = p.t[2];
   const float fx = c.fx, fy = c.fy;
-  const float itz = 1.f / tz, itz2 = itz * itz;
+  const float itz = __builtin_amdgcn_rcpf(tz), itz2 = itz * itz;
   float gt[3] = {0.f, 0.f, 0.f};
   gt[2] += gJ00 * (-fx * itz2) + gJ11 * (-fy * itz2) + gJ02 * (fx * p.u * itz2) +
            gJ12 * (fy * p.v * itz2);

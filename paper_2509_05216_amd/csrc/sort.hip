@@ -357,7 +357,18 @@ __global__ __launch_bounds__(256) void k_emit(ViewTable vt, int n_gauss,
     const uint32_t ol = (uint32_t)__shfl((int)o, l, 64);
     const uint32_t il = (uint32_t)__shfl((int)idx, l, 64);
     if (act) {
-      const uint32_t yy = li / wl, xx = li - yy * wl;
+      // row and column of the record in its rectangle: a float reciprocal
+      // estimate of li / wl is off by at most one below 2^20, so one step
+      // corrects it (exact integer division beyond)
+      uint32_t yy;
+      if (li < (1u << 20)) {
+        yy = (uint32_t)((float)li * __builtin_amdgcn_rcpf((float)wl));
+        const int32_t rem = (int32_t)(li - yy * wl);
+        yy = rem < 0 ? yy - 1u : (rem >= (int32_t)wl ? yy + 1u : yy);
+      } else {
+        yy = li / wl;
+      }
+      const uint32_t xx = li - yy * wl;
       tkey[ol + li] = k0 + yy * txl + xx;
       tval[ol + li] = il;
     }

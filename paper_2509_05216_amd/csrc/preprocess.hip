@@ -601,7 +601,7 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd_one(ParamsDev prm, ViewT
 // The direction gradient of channel c is sum_j sh[j][c] grad Y_j, scaled by the
 // view's colour gradient in c.
 template <int DEG, int kShViews>
-__global__ __launch_bounds__(256) void k_preprocess_bwd_sh(ParamsDev prm, ViewTable vt,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_preprocess_bwd_sh(ParamsDev prm, ViewTable vt,
                                                            float* __restrict__ accC,
                                                            const uint8_t* __restrict__ clampm,
                                                            GradsDev gout) {

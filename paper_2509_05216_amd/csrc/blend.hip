@@ -28,10 +28,14 @@
 // accumulators with one global atomic per component per (tile, Gaussian).
 //
 // Both walks are branch-free per pair (lanes that skip a pair select zeros),
-// keep two slots' LDS operands in flight, and take each slot index from a
-// 64-entry VGPR copy of the wave's list through readlane.  A staged splat
-// carries its conic pre-scaled by -log2(e)/2 (one fused quadratic and one
-// v_exp per pair) and its mean relative to the tile origin.  Both kernels
+// keep two slots' LDS operands in flight, and read the wave's list (slot byte
+// offsets) four or two entries at a time straight into VGPRs that address the
+// slot data.  The forward keeps its stopped lanes as a wave mask, so its
+// per-pair use/stop decisions are scalar operations on comparison ballots; the
+// backward's flush transforms each slot's sums in place before the global
+// atomics.  A staged splat carries its conic pre-scaled by -log2(e)/2 (one
+// fused quadratic and one v_exp per pair) and its mean relative to the tile
+// origin.  Both kernels
 // evaluate the skip/stop decisions with the same inline code on the same
 // staged values (the library is compiled with -ffp-contract=off, and the
 // fused operations are explicit), so the backward reproduces the forward's

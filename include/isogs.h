@@ -84,8 +84,8 @@ typedef struct {
  * clipped to the tile's pixel count for tile 8); bg = background colour;
  * flags: GS_RENDER_PERSISTENT blends all views' tiles with one persistent
  * launch (a resident grid draining a work queue), GS_RENDER_LONGEST_FIRST
- * orders that queue by descending tile list length.  Results do not depend
- * on the flags. */
+ * orders that queue by descending tile list length (to within 1/16 of an
+ * octave).  Results do not depend on the flags. */
 enum { GS_RENDER_PERSISTENT = 1, GS_RENDER_LONGEST_FIRST = 2 };
 typedef struct {
   int32_t tile;

@@ -81,25 +81,13 @@ __global__ __launch_bounds__(kThreads) void k_scan_reduce(F f, uint32_t n, uint6
   if (threadIdx.x == 0) partial[blockIdx.x] = total;
 }
 
-// Single block: exclusive scan of the block partials in place; total to *d_total.
-__global__ __launch_bounds__(kThreads) void k_scan_partials(uint64_t* partial, uint32_t nb,
-                                                            uint64_t* d_total) {
-  __shared__ uint64_t sw[kWaves];
-  uint64_t carry = 0;
-  for (uint32_t base = 0; base < nb; base += kThreads) {
-    const uint32_t i = base + threadIdx.x;
-    const uint64_t x = (i < nb) ? partial[i] : 0ull;
-    uint64_t total;
-    const uint64_t ex = block_exclusive_scan(x, sw, total);
-    if (i < nb) partial[i] = carry + ex;
-    carry += total;
-  }
-  if (threadIdx.x == 0 && d_total != nullptr) *d_total = carry;
-}
-
+// Down-sweep: each block forms its carry-in by summing the totals of the
+// blocks before it (a few thousand at most, read from L2), so no separate
+// single-block scan of the totals is launched; the last block also writes the
+// grand total when d_total is given.
 template <class F>
 __global__ __launch_bounds__(kThreads) void k_scan_down(F f, uint32_t n, const uint64_t* partial,
-                                                        uint32_t* out) {
+                                                        uint32_t* out, uint64_t* d_total) {
   __shared__ uint64_t sw[kWaves];
   // striped (coalesced) loads and stores, transposed through LDS so that each
   // thread scans kItems consecutive elements; one pad word per 32 avoids bank conflicts
@@ -120,8 +108,13 @@ __global__ __launch_bounds__(kThreads) void k_scan_down(F f, uint32_t n, const u
     v[j] = buf[p + (p >> 5)];
     s += v[j];
   }
+  uint64_t carry = 0;
+  for (uint32_t b = threadIdx.x; b < blockIdx.x; b += kThreads) carry += partial[b];
+  uint64_t ctot;
+  block_exclusive_scan(carry, sw, ctot);  // ctot: the sum over all threads
   uint64_t total;
-  uint64_t run = block_exclusive_scan(s, sw, total) + partial[blockIdx.x];
+  uint64_t run = block_exclusive_scan(s, sw, total) + ctot;
+  if (d_total != nullptr && blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) *d_total = ctot + total;
 #pragma unroll
   for (int j = 0; j < kItems; ++j) {
     const uint32_t p = threadIdx.x * kItems + j;
@@ -478,9 +471,8 @@ gs_status scan_tile_counts(Ctx* ctx, SortScratch& ss, const uint32_t* sidx, cons
   auto* partial = (uint64_t*)ss.partial.p;
   hipLaunchKernelGGL(k_scan_reduce<ArrayIn>, dim3(nb), dim3(kThreads), 0, s, f, n, partial);
   GS_LAUNCHED("scan_reduce");
-  hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kThreads), 0, s, partial, nb, d_total);
-  GS_LAUNCHED("scan_partials");
-  hipLaunchKernelGGL(k_scan_down<ArrayIn>, dim3(nb), dim3(kThreads), 0, s, f, n, partial, offs);
+  hipLaunchKernelGGL(k_scan_down<ArrayIn>, dim3(nb), dim3(kThreads), 0, s, f, n, partial, offs,
+                     d_total);
   GS_LAUNCHED("scan_down");
   return GS_OK;
 }
@@ -508,11 +500,8 @@ gs_status sort_pairs_u32(Ctx* ctx, SortScratch& ss, const uint32_t* kin, const u
     ArrayIn f{hist};
     hipLaunchKernelGGL(k_scan_reduce<ArrayIn>, dim3(hb), dim3(kThreads), 0, s, f, hist_n, partial);
     GS_LAUNCHED("radix_scan_reduce");
-    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kThreads), 0, s, partial, hb,
-                       (uint64_t*)nullptr);
-    GS_LAUNCHED("radix_scan_partials");
     hipLaunchKernelGGL(k_scan_down<ArrayIn>, dim3(hb), dim3(kThreads), 0, s, f, hist_n, partial,
-                       hist);
+                       hist, (uint64_t*)nullptr);
     GS_LAUNCHED("radix_scan_down");
     hipLaunchKernelGGL(k_radix_scatter, dim3(nb), dim3(kThreads), 0, s, ki, vi, kb[out], vb[out],
                        n, d_n, shift, nb, hist);

@@ -174,13 +174,33 @@ __global__ __launch_bounds__(kThreads) void k_radix_hist(const uint32_t* __restr
       q[j].w = ~0u;
     }
   }
+  // A digit shared by many lanes of the wave (the high bytes of depths, the
+  // tile rows of neighbouring records) would serialise their LDS atomics on one
+  // word: the lanes holding lane 0's digit, and those holding the digit of the
+  // first lane left, are counted by one atomic each; the rest add one apiece.
 #pragma unroll
   for (int j = 0; j < kItems / 4; ++j) {
     const uint32_t i = base + 4u * (j * 64 + lane);
     const uint32_t kk[4] = {q[j].x, q[j].y, q[j].z, q[j].w};
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
-      if (i + u < n) atomicAdd(&h[wave][(kk[u] >> shift) & 0xffu], 1u);
+    for (int u = 0; u < 4; ++u) {
+      const bool ok = i + u < n;
+      const uint32_t d = (kk[u] >> shift) & 0xffu;
+      const uint32_t d0 = __builtin_amdgcn_readfirstlane(d);
+      const uint64_t m0 = __builtin_amdgcn_ballot_w64(ok && d == d0);
+      const uint64_t r0 = __builtin_amdgcn_ballot_w64(ok && d != d0);
+      uint32_t d1 = 0x100u;  // no digit
+      uint64_t m1 = 0;
+      if (r0 != 0) {
+        d1 = (uint32_t)__builtin_amdgcn_readlane((int)d, __builtin_ctzll(r0));
+        m1 = __builtin_amdgcn_ballot_w64(ok && d == d1);
+      }
+      if (lane == 0) {
+        if (m0 != 0) atomicAdd(&h[wave][d0], (uint32_t)__popcll(m0));
+        if (m1 != 0) atomicAdd(&h[wave][d1], (uint32_t)__popcll(m1));
+      }
+      if (ok && d != d0 && d != d1) atomicAdd(&h[wave][d], 1u);
+    }
   }
   __syncthreads();
   for (int d = threadIdx.x; d < kRadix; d += kThreads) {
@@ -208,8 +228,16 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(
   const int wave = threadIdx.x / 64, lane = __lane_id();
   for (int d = threadIdx.x; d < kWaves * kRadix; d += kThreads) (&cnt[0][0])[d] = 0;
   const uint32_t n = load_n(n_max, d_n);
-  const uint32_t base = blockIdx.x * (uint32_t)kChunk + wave * 64 * kItems;
-  if (blockIdx.x * (uint32_t)kChunk >= n) return;  // whole block empty (uniform)
+  // Chunk of this block.  Workgroups go to the eight XCDs in turn; the
+  // bijection below gives each XCD a contiguous run of chunks instead (the last
+  // nblocks % 8 keep their place), so the runs that neighbouring chunks write
+  // for one digit, which are adjacent in the output, meet in the same L2 and
+  // the cache lines they share are written back whole.
+  const uint32_t n8 = nblocks / 8;
+  const uint32_t chunk =
+      blockIdx.x < 8 * n8 ? (blockIdx.x % 8) * n8 + blockIdx.x / 8 : blockIdx.x;
+  const uint32_t base = chunk * (uint32_t)kChunk + wave * 64 * kItems;
+  if (chunk * (uint32_t)kChunk >= n) return;  // whole block empty (uniform)
   uint32_t key[kItems], val[kItems], rank[kItems];
 #pragma unroll
   for (int j = 0; j < kItems; ++j) {
@@ -261,7 +289,7 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(
     uint64_t total;
     const uint32_t start = (uint32_t)block_exclusive_scan(run, scan_tmp, total);
     lstart[d] = start;
-    gofs[d] = hist_scanned[(size_t)d * nblocks + blockIdx.x] - start;
+    gofs[d] = hist_scanned[(size_t)d * nblocks + chunk] - start;
   }
   __syncthreads();
 #pragma unroll
@@ -275,7 +303,7 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(
     }
   }
   __syncthreads();
-  const uint32_t nloc = min((uint32_t)kChunk, n - blockIdx.x * (uint32_t)kChunk);
+  const uint32_t nloc = min((uint32_t)kChunk, n - chunk * (uint32_t)kChunk);
   for (uint32_t t = threadIdx.x; t < nloc; t += kThreads) {
     const uint32_t k = sk[t];
     const uint32_t pos = gofs[(k >> shift) & 0xffu] + t;

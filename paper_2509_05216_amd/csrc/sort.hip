@@ -149,6 +149,15 @@ __global__ __launch_bounds__(256) void k_counts(const uint32_t* __restrict__ sid
 }
 
 // ---------------------------------------------------------------- radix sort
+// Chunk of this block (grid of nblocks blocks).  Workgroups go to the eight
+// XCDs in turn, so consecutive block indices land in different L2s; this
+// bijection gives each XCD a contiguous run of chunks instead (the last
+// nblocks % 8 keep their place).
+__device__ inline uint32_t xcd_chunk(uint32_t nblocks) {
+  const uint32_t n8 = nblocks / 8;
+  return blockIdx.x < 8 * n8 ? (blockIdx.x % 8) * n8 + blockIdx.x / 8 : blockIdx.x;
+}
+
 __global__ __launch_bounds__(kThreads) void k_radix_hist(const uint32_t* __restrict__ keys,
                                                          uint32_t n_max, const uint32_t* d_n,
                                                          int shift, uint32_t nblocks,
@@ -158,9 +167,13 @@ __global__ __launch_bounds__(kThreads) void k_radix_hist(const uint32_t* __restr
   for (int d = threadIdx.x; d < kWaves * kRadix; d += kThreads) (&h[0][0])[d] = 0;
   __syncthreads();
   const uint32_t n = load_n(n_max, d_n);
+  // chunk of this block: XCD-contiguous as in k_radix_scatter, so that the
+  // counts of neighbouring chunks, adjacent in every digit's row of the table,
+  // are written through the same L2
+  const uint32_t chunk = xcd_chunk(nblocks);
   // the wave's 1024 keys as four 16-byte reads per lane, all issued before the
   // counting (the order of counting does not matter)
-  const uint32_t base = blockIdx.x * (uint32_t)kChunk + wave * 64 * kItems;
+  const uint32_t base = chunk * (uint32_t)kChunk + wave * 64 * kItems;
   uint4 q[kItems / 4];
 #pragma unroll
   for (int j = 0; j < kItems / 4; ++j) {
@@ -206,7 +219,7 @@ __global__ __launch_bounds__(kThreads) void k_radix_hist(const uint32_t* __restr
   for (int d = threadIdx.x; d < kRadix; d += kThreads) {
     uint32_t s = 0;
     for (int w = 0; w < kWaves; ++w) s += h[w][d];
-    hist[(size_t)d * nblocks + blockIdx.x] = s;
+    hist[(size_t)d * nblocks + chunk] = s;
   }
 }
 
@@ -228,14 +241,10 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(
   const int wave = threadIdx.x / 64, lane = __lane_id();
   for (int d = threadIdx.x; d < kWaves * kRadix; d += kThreads) (&cnt[0][0])[d] = 0;
   const uint32_t n = load_n(n_max, d_n);
-  // Chunk of this block.  Workgroups go to the eight XCDs in turn; the
-  // bijection below gives each XCD a contiguous run of chunks instead (the last
-  // nblocks % 8 keep their place), so the runs that neighbouring chunks write
-  // for one digit, which are adjacent in the output, meet in the same L2 and
-  // the cache lines they share are written back whole.
-  const uint32_t n8 = nblocks / 8;
-  const uint32_t chunk =
-      blockIdx.x < 8 * n8 ? (blockIdx.x % 8) * n8 + blockIdx.x / 8 : blockIdx.x;
+  // the runs that neighbouring chunks write for one digit, adjacent in the
+  // output, meet in the same L2, and the cache lines they share are written
+  // back whole
+  const uint32_t chunk = xcd_chunk(nblocks);
   const uint32_t base = chunk * (uint32_t)kChunk + wave * 64 * kItems;
   if (chunk * (uint32_t)kChunk >= n) return;  // whole block empty (uniform)
   uint32_t key[kItems], val[kItems], rank[kItems];

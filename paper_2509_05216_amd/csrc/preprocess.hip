@@ -592,129 +592,156 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd_one(ParamsDev prm, ViewT
   put(gout.logits + i, g_logit);
 }
 
+// g = sum_j w[j] grad Y_j at the unit direction (x, y, z): the same terms as
+// sh_basis_grad_dot, with each weight scaled once and the terms fused into
+// multiply-adds (the backward takes no binning decision, so its rounding is
+// free to differ from the forward's).
+__device__ inline void sh_grad_w(float x, float y, float z, int deg, const float* w, float& gx,
+                                 float& gy, float& gz) {
+  gx = gy = gz = 0.f;
+  if (deg < 1) return;
+  gx = -kK1 * w[3];
+  gy = -kK1 * w[1];
+  gz = kK1 * w[2];
+  if (deg < 2) return;
+  const float xx = x * x, yy = y * y, zz = z * z;
+  float t = kK2 * w[4];
+  gx = fmaf(y, t, gx);
+  gy = fmaf(x, t, gy);
+  t = kK2 * w[5];
+  gy = fmaf(-z, t, gy);
+  gz = fmaf(-y, t, gz);
+  t = 2.f * kK3 * w[6];
+  gx = fmaf(-x, t, gx);
+  gy = fmaf(-y, t, gy);
+  gz = fmaf(2.f * z, t, gz);
+  t = kK2 * w[7];
+  gx = fmaf(-z, t, gx);
+  gz = fmaf(-x, t, gz);
+  t = kK2 * w[8];
+  gx = fmaf(x, t, gx);
+  gy = fmaf(-y, t, gy);
+  if (deg < 3) return;
+  const float xy = x * y, yz = y * z, xz = x * z, dxy = xx - yy;
+  t = kA3 * w[9];
+  gx = fmaf(-6.f * xy, t, gx);
+  gy = fmaf(-3.f * dxy, t, gy);
+  t = kB3 * w[10];
+  gx = fmaf(yz, t, gx);
+  gy = fmaf(xz, t, gy);
+  gz = fmaf(xy, t, gz);
+  t = kC3 * w[11];
+  gx = fmaf(2.f * xy, t, gx);
+  gy = fmaf(-(4.f * zz - xx - 3.f * yy), t, gy);
+  gz = fmaf(-8.f * yz, t, gz);
+  t = kE3 * w[12];
+  gx = fmaf(-6.f * xz, t, gx);
+  gy = fmaf(-6.f * yz, t, gy);
+  gz = fmaf(6.f * zz - 3.f * xx - 3.f * yy, t, gz);
+  t = kC3 * w[13];
+  gx = fmaf(-(4.f * zz - 3.f * xx - yy), t, gx);
+  gy = fmaf(2.f * xy, t, gy);
+  gz = fmaf(-8.f * xz, t, gz);
+  t = kB3 * w[14];
+  gx = fmaf(xz, t, gx);
+  gy = fmaf(-yz, t, gy);
+  gz = fmaf(0.5f * dxy, t, gz);
+  t = kA3 * w[15];
+  gx = fmaf(-3.f * dxy, t, gx);
+  gy = fmaf(6.f * xy, t, gy);
+}
+
 // Colour part; runs after k_preprocess_bwd_geom (it adds to the mean gradient
-// that kernel wrote) and clears every accumulator it finds non-zero.  Views are
-// taken kShViews (4) at a time, and within a chunk the colour channel is
-// outermost:
-// per channel only that channel's coefficients and gradient sums are live,
-// while each view keeps its direction, colour gradient and direction gradient.
-// The direction gradient of channel c is sum_j sh[j][c] grad Y_j, scaled by the
-// view's colour gradient in c.
-template <int DEG, int kShViews>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_preprocess_bwd_sh(ParamsDev prm, ViewTable vt,
-                                                           float* __restrict__ accC,
-                                                           const uint8_t* __restrict__ clampm,
-                                                           GradsDev gout) {
+// that kernel wrote) and clears every accumulator it finds non-zero.  All of
+// the Gaussian's coefficients and their gradient sums stay in registers while
+// the views are walked one at a time, so each view's basis is evaluated once,
+// and its direction gradient is one weighted basis gradient: the weight of
+// basis j is sum_c dL/dcolour_c sh[j][c].  The next view's colour sums and
+// clamp mask are loaded while the current one is processed.
+template <int DEG>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_preprocess_bwd_sh(
+    ParamsDev prm, ViewTable vt, float* __restrict__ accC, const uint8_t* __restrict__ clampm,
+    GradsDev gout) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int n = prm.n;
   if (i >= n) return;
   constexpr int deg = DEG;
   constexpr int nb = (DEG + 1) * (DEG + 1);
   const bool add = gout.accumulate != 0;
+  float4* const acc4 = reinterpret_cast<float4*>(accC);
+  float4 a_next = acc4[i];
+  uint32_t m_next = clampm[i];
+  float mf[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) mf[k] = prm.means[(size_t)k * n + i];
+  float sh[nb][3], gsh[nb][3];
+#pragma unroll
+  for (int j = 0; j < nb; ++j)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      sh[j][c] = prm.sh[(size_t)(j * 3 + c) * n + i];
+      gsh[j][c] = 0.f;
+    }
   float gmf[3] = {0.f, 0.f, 0.f};
-  float mf[3] = {0.f, 0.f, 0.f};
-  bool mf_loaded = false, wrote = false;
-  for (int v0 = 0; v0 < vt.n; v0 += kShViews) {
-    float d[kShViews][3], inv[kShViews], gr[kShViews][3], gd[kShViews][3];
-    bool act = false;
-    bool live[kShViews];  // some lane of the wave has a colour gradient in this view
-#pragma unroll
-    for (int c = 0; c < kShViews; ++c) {
-      d[c][0] = d[c][1] = d[c][2] = 0.f;
-      gr[c][0] = gr[c][1] = gr[c][2] = 0.f;
-      gd[c][0] = gd[c][1] = gd[c][2] = 0.f;
-      inv[c] = 0.f;
-      const int v = v0 + c;
-      if (v < vt.n) {
-        // untouched entries, and touched ones without gradient, are zero
-        const size_t o = (size_t)v * n + i;
-        {
-          float4* a = reinterpret_cast<float4*>(accC + o * kAccC);
-          const float4 a0 = a[0];
-          const bool col = a0.x != 0.f || a0.y != 0.f || a0.z != 0.f;
-          if (col) {
-            a[0] = make_float4(0.f, 0.f, 0.f, 0.f);  // cleared for the next backward pass
-            const uint32_t mask = clampm[o];
-            gr[c][0] = (mask & 1u) ? 0.f : a0.x;
-            gr[c][1] = (mask & 2u) ? 0.f : a0.y;
-            gr[c][2] = (mask & 4u) ? 0.f : a0.z;
-            if (!mf_loaded) {
-              for (int k = 0; k < 3; ++k) mf[k] = prm.means[k * n + i];
-              mf_loaded = true;
-            }
-            const CamDev& cam = vt.v[v];
-            const float dx = mf[0] - cam.campos[0], dy = mf[1] - cam.campos[1],
-                        dz = mf[2] - cam.campos[2];
-            inv[c] = 1.0f / sqrtf(dx * dx + dy * dy + dz * dz);
-            d[c][0] = dx * inv[c];
-            d[c][1] = dy * inv[c];
-            d[c][2] = dz * inv[c];
-            act = true;
-          }
-        }
-      }
-      live[c] = __builtin_amdgcn_ballot_w64(gr[c][0] != 0.f || gr[c][1] != 0.f ||
-                                            gr[c][2] != 0.f) != 0;
-    }
-    if (!act) continue;
-    // views without colour gradient have gr = 0 and contribute nothing
-    // coefficients of channel ch + 1 are loaded while channel ch is processed
-    float shn[16];
-#pragma unroll
-    for (int j = 0; j < nb; ++j) shn[j] = prm.sh[(size_t)(j * 3) * n + i];
+  bool any_col = false;
 #pragma unroll 1
-    for (int ch = 0; ch < 3; ++ch) {
-      float shc[16], gsh[16];
-#pragma unroll
-      for (int j = 0; j < nb; ++j) {
-        shc[j] = shn[j];
-        gsh[j] = 0.f;
-      }
-      if (ch < 2) {
-#pragma unroll
-        for (int j = 0; j < nb; ++j) shn[j] = prm.sh[(size_t)(j * 3 + ch + 1) * n + i];
-      }
-#pragma unroll
-      for (int c = 0; c < kShViews; ++c) {
-        if (!live[c]) continue;  // wave-uniform: no lane has work in this view
-        // the basis depends on the view only; the empty asm keeps the compiler from
-        // hoisting all views' basis terms out of the channel loop (register bound)
-        float x = d[c][0], y = d[c][1], z = d[c][2];
-        asm volatile("" : "+v"(x), "+v"(y), "+v"(z));
-        float Y[16];
-        sh_basis(x, y, z, deg, Y);
-        const float g = gr[c][ch];
-#pragma unroll
-        for (int j = 0; j < nb; ++j) gsh[j] += Y[j] * g;
-        float gx = 0.f, gy = 0.f, gz = 0.f;
-        sh_basis_grad_dot(x, y, z, deg, shc, gx, gy, gz);
-        gd[c][0] += g * gx;
-        gd[c][1] += g * gy;
-        gd[c][2] += g * gz;
-      }
-#pragma unroll
-      for (int j = 0; j < nb; ++j) {
-        float* dst = gout.sh + (size_t)(j * 3 + ch) * n + i;
-        if (wrote || add)
-          *dst += gsh[j];
-        else
-          *dst = gsh[j];
-      }
+  for (int v = 0; v < vt.n; ++v) {
+    const float4 a0 = a_next;
+    const uint32_t mask = m_next;
+    if (v + 1 < vt.n) {
+      const size_t on = (size_t)(v + 1) * n + i;
+      a_next = acc4[on];
+      m_next = clampm[on];
     }
-    wrote = true;
-#pragma unroll
-    for (int c = 0; c < kShViews; ++c) {
-      const float dot = gd[c][0] * d[c][0] + gd[c][1] * d[c][1] + gd[c][2] * d[c][2];
-#pragma unroll
-      for (int k = 0; k < 3; ++k) gmf[k] += (gd[c][k] - d[c][k] * dot) * inv[c];
+    // untouched entries, and touched ones without gradient, are zero
+    const bool col = a0.x != 0.f || a0.y != 0.f || a0.z != 0.f;
+    if (__builtin_amdgcn_ballot_w64(col) == 0) continue;  // no lane of the wave has work
+    if (col) {
+      acc4[(size_t)v * n + i] = make_float4(0.f, 0.f, 0.f, 0.f);  // cleared for the next pass
+      any_col = true;
     }
+    const float gr0 = (col && !(mask & 1u)) ? a0.x : 0.f;
+    const float gr1 = (col && !(mask & 2u)) ? a0.y : 0.f;
+    const float gr2 = (col && !(mask & 4u)) ? a0.z : 0.f;
+    const CamDev& cam = vt.v[v];
+    const float dx = mf[0] - cam.campos[0], dy = mf[1] - cam.campos[1],
+                dz = mf[2] - cam.campos[2];
+    const float inv = col ? 1.0f / sqrtf(dx * dx + dy * dy + dz * dz) : 0.f;
+    const float x = dx * inv, y = dy * inv, z = dz * inv;
+    float Y[16], w[16];
+    sh_basis(x, y, z, deg, Y);
+#pragma unroll
+    for (int j = 0; j < nb; ++j) {
+      gsh[j][0] = fmaf(Y[j], gr0, gsh[j][0]);
+      gsh[j][1] = fmaf(Y[j], gr1, gsh[j][1]);
+      gsh[j][2] = fmaf(Y[j], gr2, gsh[j][2]);
+      w[j] = fmaf(gr2, sh[j][2], fmaf(gr1, sh[j][1], gr0 * sh[j][0]));
+    }
+    float gx, gy, gz;
+    sh_grad_w(x, y, z, deg, w, gx, gy, gz);
+    // through the normalisation d = (mu - campos) / |mu - campos|
+    const float dot = gx * x + gy * y + gz * z;
+    gmf[0] += (gx - x * dot) * inv;
+    gmf[1] += (gy - y * dot) * inv;
+    gmf[2] += (gz - z * dot) * inv;
   }
-  if (mf_loaded)
+  if (any_col) {
+#pragma unroll
     for (int k = 0; k < 3; ++k) gout.means[(size_t)k * n + i] += gmf[k];
-  if (!wrote && !add)
+#pragma unroll
+    for (int j = 0; j < nb; ++j)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        float* dst = gout.sh + (size_t)(j * 3 + c) * n + i;
+        if (add)
+          *dst += gsh[j][c];
+        else
+          *dst = gsh[j][c];
+      }
+  } else if (!add) {
     for (int j = 0; j < nb * 3; ++j) gout.sh[(size_t)j * n + i] = 0.f;
+  }
 }
-
 
 }  // namespace
 
@@ -760,10 +787,10 @@ gs_status launch_preprocess_bwd(const ParamsDev& p, const ViewTable& vt, Frame& 
   hipLaunchKernelGGL(k_preprocess_bwd_geom, dim3(blocks), dim3(256), 0, s, p, vt, accG, g);
   GS_LAUNCHED("preprocess_bwd_geom");
   switch (p.sh_degree) {
-    case 0: go(k_preprocess_bwd_sh<0, 4>); break;
-    case 1: go(k_preprocess_bwd_sh<1, 4>); break;
-    case 2: go(k_preprocess_bwd_sh<2, 4>); break;
-    default: go(k_preprocess_bwd_sh<3, 4>); break;
+    case 0: go(k_preprocess_bwd_sh<0>); break;
+    case 1: go(k_preprocess_bwd_sh<1>); break;
+    case 2: go(k_preprocess_bwd_sh<2>); break;
+    default: go(k_preprocess_bwd_sh<3>); break;
   }
   GS_LAUNCHED("preprocess_bwd_sh");
   return GS_OK;

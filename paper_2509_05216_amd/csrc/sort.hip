@@ -130,9 +130,9 @@ __global__ __launch_bounds__(kThreads) void k_scan_down(F f, uint32_t n, const u
   }
 }
 
-// Tile count of every (view, Gaussian) entry in depth order (one gather).
-// The one random gather of the rectangles: tile counts in depth order, and the
-// rectangles themselves in that order for the emission.
+// The one random gather of the rectangles: the tile count of every (view,
+// Gaussian) entry in depth order, and the rectangles themselves in that order
+// for the emission.
 __global__ __launch_bounds__(256) void k_counts(const uint32_t* __restrict__ sidx,
                                                 const uint2* __restrict__ rect, uint32_t n,
                                                 uint32_t* __restrict__ counts,

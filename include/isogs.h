@@ -124,7 +124,8 @@ typedef struct {
   int32_t tile;
   int64_t n_gaussians;
   int64_t n_records;        /* K: (Gaussian, tile) records over all views */
-  int64_t n_visible;        /* (view, Gaussian) pairs touching >= 1 tile */
+  int64_t n_visible;        /* (view, Gaussian) pairs touching >= 1 tile (after a step
+                               graph replay: that replay's, once gs_step_graph_sync ran) */
   int64_t n_tiles;          /* tiles over all views */
   int64_t n_pixels;         /* pixels over all views */
   int64_t device_bytes;     /* device memory held by the frame */
@@ -200,7 +201,11 @@ gs_status gs_init_from_points(gs_ctx* ctx, const float* xyz, int64_t n,
                               gs_params out, void* stream);
 
 /* Forward render of n_views views (1..16) of one scene: EWA projection and
- * SH colour, tile binning and sort, front-to-back compositing.  images[v]
+ * SH colour, tile binning and sort, front-to-back compositing.  This is the
+ * differentiable renderer of the 3D-GS model that Sec. III (Method Overview)
+ * trains to match the orbit views; the paper adopts it by citation (Sec. I,
+ * III) without restating it, so the readings of the projection, colour and
+ * compositing conventions are those of the standard 3D-GS rasterizer.  images[v]
  * (device, [3][H_v][W_v]) receives view v.  `*state` receives the frame that
  * the backward pass needs; pass a previous frame to reuse its memory, or
  * NULL to create one (release with gs_frame_release).  The record count is
@@ -213,24 +218,42 @@ gs_status gs_render_fwd(gs_ctx* ctx, gs_params params, const gs_camera* cams,
 /* Training loss of n_views rendered images against targets and its image
  * gradient: mean over views of (1 - lambda) L1 + lambda (1 - SSIM), SSIM with
  * an 11x11 Gaussian window (sigma 1.5), C1 = 1e-4, C2 = 9e-4, zero padding.
- * loss_out: device float (may be NULL); dl_dimg[v]: device [3][H_v][W_v]. */
+ * The objective with which the splatting model "is trained to match these
+ * views" (Sec. III); its form is the 3D-GS training loss, which the paper
+ * uses without stating it (SSIM is also one of its quality metrics, Sec. IV).
+ * loss_out: device float (may be NULL); dl_dimg[v]: device [3][H_v][W_v]
+ * (NULL: the loss value only).  The context's loss workspace grows to the
+ * largest view seen; calls on one context must not overlap on different
+ * streams (they share that workspace). */
 gs_status gs_loss_grad(gs_ctx* ctx, const float* const* rendered,
                        const float* const* target, const gs_camera* cams,
                        int32_t n_views, float lambda_dssim, float* loss_out,
                        float* const* dl_dimg, void* stream);
 
-/* Backward of gs_render_fwd for the frame's views: reverse front-to-back
- * traversal that recomputes transmittance (no per-pixel lists are stored),
- * then the chain rule to every parameter.  dl_dimg[v] as above.  grads
- * (device, caller-owned, same shapes as params) receive the gradient summed
- * over the views; accumulate != 0 adds to their contents instead. */
+/* Backward of gs_render_fwd for the frame's views (the gradient step of the
+ * 3D-GS training adopted in Sec. III): reverse front-to-back traversal that
+ * recomputes transmittance (no per-pixel lists are stored), then the chain
+ * rule to every parameter.  dl_dimg[v] as above.  grads (device,
+ * caller-owned, same shapes as params) receive the gradient summed over the
+ * views; flags:
+ *   GS_BWD_ACCUMULATE    add to the contents of grads instead of writing them;
+ *   GS_BWD_KEEP_SCREEN   leave the per-(view, Gaussian) screen-space sums of
+ *                        the traversal in the frame (gs_frame_export
+ *                        GS_EXPORT_SCREEN_GRADS); the next gs_render_fwd on
+ *                        the frame clears them, and a second backward before it
+ *                        fails with GS_ERR_INVALID.
+ * Without GS_BWD_KEEP_SCREEN the sums are consumed and cleared, so one
+ * forward supports one backward. */
+enum { GS_BWD_ACCUMULATE = 1, GS_BWD_KEEP_SCREEN = 2 };
 gs_status gs_render_bwd(gs_ctx* ctx, gs_frame* frame, gs_params params,
                         const float* const* dl_dimg, gs_params grads,
-                        int32_t accumulate, void* stream);
+                        int32_t flags, void* stream);
 
 /* One fused, bias-corrected Adam step over every parameter group (step
- * counts from 1).  p, m, v updated in place; g read (and cleared if
- * opts->zero_grads). */
+ * counts from 1): the optimiser of the 3D-GS training the paper adopts
+ * (Sec. III), applied once per step to the gradient of all views of the step,
+ * as after the paper's gradient all-reduce.  p, m, v updated in place; g read
+ * (and cleared if opts->zero_grads). */
 gs_status gs_adam_step(gs_ctx* ctx, gs_params p, gs_params g, gs_params m,
                        gs_params v, const gs_adam_opts* opts, int64_t step,
                        void* stream);

@@ -254,13 +254,23 @@ def loss_grad(ctx, rendered, targets, cams, lam=0.2, *, want_grad=True, stream=N
     return loss, grads
 
 
-def render_bwd(ctx, frame, params, dl_dimg, grads=None, *, accumulate=False, stream=None):
+BWD_ACCUMULATE = 1
+BWD_KEEP_SCREEN = 2
+
+
+def render_bwd(ctx, frame, params, dl_dimg, grads=None, *, accumulate=False, keep_screen=False,
+               stream=None):
+    """Parameter gradients of the frame's forward for upstream image gradients.
+
+    keep_screen: leave the screen-space sums in the frame for
+    ``frame.export("screen_grads")`` (the next forward clears them)."""
     if grads is None:
         grads = params.zeros_like() if accumulate else Params(
             *(torch.empty_like(t) for t in params.tensors()), params.sh_degree)
     da, keep = L.ptr_array([d.contiguous().data_ptr() for d in dl_dimg])
+    flags = (BWD_ACCUMULATE if accumulate else 0) | (BWD_KEEP_SCREEN if keep_screen else 0)
     L.check(L.lib().gs_render_bwd(ctx.handle, frame.handle, params.abi(), da, grads.abi(),
-                                  1 if accumulate else 0, _stream(stream)))
+                                  flags, _stream(stream)))
     return grads
 
 

@@ -23,7 +23,7 @@ gs_status hip_fail(hipError_t e, const char* what) {
   return (e == hipErrorOutOfMemory) ? GS_ERR_NOMEM : GS_ERR_HIP;
 }
 
-gs_status buf_ensure(Ctx* ctx, DevBuf& b, size_t bytes) {
+gs_status buf_ensure(Ctx* ctx, DevBuf& b, size_t bytes, hipStream_t s, hipEvent_t prior) {
   if (bytes <= b.cap) return GS_OK;
   if (ctx->capturing) {
     set_error("internal: a buffer would grow (%zu -> %zu bytes) during graph capture", b.cap,
@@ -42,7 +42,9 @@ gs_status buf_ensure(Ctx* ctx, DevBuf& b, size_t bytes) {
     }
   }
   if (b.p != nullptr) {
-    GS_HIP(hipDeviceSynchronize());  // queued work may still use the old buffer
+    // work queued on s, and before `prior`, may still use the old buffer
+    GS_HIP(hipStreamSynchronize(s));
+    if (prior != nullptr) GS_HIP(hipEventSynchronize(prior));
     GS_HIP(hipFree(b.p));
     {
       std::lock_guard<std::mutex> lk(ctx->mem_mutex);
@@ -161,6 +163,9 @@ static void frame_free(Frame* f) {
   for (DevBuf* b : all) buf_free(c, *b);
   if (f->pinned != nullptr) (void)hipHostFree(f->pinned);
   f->pinned = nullptr;
+  if (f->last_use != nullptr) (void)hipEventDestroy(f->last_use);
+  f->last_use = nullptr;
+  f->ss.prior = nullptr;
 }
 
 static bool valid_params(const gs_params& p, const char* what) {
@@ -192,14 +197,15 @@ static bool valid_camera(const gs_camera& c, int v) {
   return true;
 }
 
-GradsDev grads_dev(const gs_params& g, int accumulate) {
+GradsDev grads_dev(const gs_params& g, int flags) {
   GradsDev d;
   d.means = g.means;
   d.log_scales = g.log_scales;
   d.quats = g.quats;
   d.logits = g.opacity_logits;
   d.sh = g.sh;
-  d.accumulate = accumulate;
+  d.accumulate = (flags & GS_BWD_ACCUMULATE) != 0;
+  d.keep_screen = (flags & GS_BWD_KEEP_SCREEN) != 0;
   return d;
 }
 
@@ -260,14 +266,19 @@ static gs_status build_views(Frame& f, const gs_camera* cams, int nv, float* con
   return GS_OK;
 }
 
-static gs_status frame_buffers(Frame& f) {
+// Sizes the frame's buffers for its views; s: the stream of the calling pass.
+static gs_status frame_buffers(Frame& f, hipStream_t s) {
   Ctx* c = f.ctx;
   const size_t vn = (size_t)f.views * (size_t)f.n;
   gs_status st;
-#define ENS(buf, bytes)                       \
-  do {                                        \
-    st = buf_ensure(c, (buf), (bytes));       \
-    if (st != GS_OK) return st;               \
+  if (f.last_use == nullptr) {
+    GS_HIP(hipEventCreateWithFlags(&f.last_use, hipEventDisableTiming));
+    f.ss.prior = f.last_use;
+  }
+#define ENS(buf, bytes)                                       \
+  do {                                                        \
+    st = buf_ensure(c, (buf), (bytes), s, f.last_use);        \
+    if (st != GS_OK) return st;                               \
   } while (0)
   ENS(f.splat, vn * 48);
   ENS(f.rect, vn * 8);
@@ -288,9 +299,10 @@ static gs_status frame_buffers(Frame& f) {
   }
 #undef ENS
   if (f.words.cap == 0) {
-    st = buf_ensure(c, f.words, kWordCount * 4);
+    st = buf_ensure(c, f.words, kWordCount * 4, s);
     if (st != GS_OK) return st;
-    st = launch_fill_u32(f.words.p, 0u, kWordCount, nullptr);
+    // cleared on the pass's own stream, ahead of the kernels that use the words
+    st = launch_fill_u32(f.words.p, 0u, kWordCount, s);
     if (st != GS_OK) return st;
   }
   if (f.pinned == nullptr) GS_HIP(hipHostMalloc((void**)&f.pinned, 64, hipHostMallocDefault));
@@ -312,7 +324,11 @@ namespace isogs {
 static void ctx_free(gs_ctx* ctx) {
   (void)hipSetDevice(ctx->device);
   (void)hipDeviceSynchronize();
-  free_loss_scratch(ctx);
+  if (ctx->loss_scratch != nullptr) {
+    loss_scratch_free(ctx, *ctx->loss_scratch);
+    delete ctx->loss_scratch;
+    ctx->loss_scratch = nullptr;
+  }
   (void)timing_collect(ctx);
   for (int i = 0; i < ctx->n_free; ++i) (void)hipEventDestroy(ctx->free_events[i]);
   delete[] ctx->free_events;
@@ -576,7 +592,7 @@ gs_status gs_render_fwd(gs_ctx* ctx, gs_params params, const gs_camera* cams, in
   f.sh_degree = params.sh_degree;
   f.K = 0;
   st = build_views(f, cams, n_views, images, bg);
-  if (st == GS_OK) st = frame_buffers(f);
+  if (st == GS_OK) st = frame_buffers(f, s);
   if (st != GS_OK) {
     if (fresh) frame_delete(fr);
     return st;
@@ -590,7 +606,10 @@ gs_status gs_render_fwd(gs_ctx* ctx, gs_params params, const gs_camera* cams, in
     f.acc_zeroed = true;
   }
   *state = fr;
-  return forward_stages(ctx, f, params_dev(params), s, 0);
+  st = forward_stages(ctx, f, params_dev(params), s, 0);
+  if (st != GS_OK) return st;
+  GS_HIP(hipEventRecord(f.last_use, s));
+  return GS_OK;
 }
 
 }  // extern "C"
@@ -620,11 +639,13 @@ gs_status forward_stages(Ctx* ctx, Frame& f, const ParamsDev& pd, hipStream_t s,
                         vn, nullptr, 32, &in_b, s);
   }
   if (st != GS_OK) return st;
+  uint32_t* words = (uint32_t*)f.words.p;
+  st = launch_visible_count(f.ss, vn, words + kWordVisible, s);
+  if (st != GS_OK) return st;
   f.sidx_sel = in_b;
   const uint32_t* sidx = (const uint32_t*)f.sidx[in_b].p;
   // 3. record offsets and the total K; the depth sort's key buffers are free now
   // and take the rectangles in depth order (x0|y0 words, x1|y1 words)
-  uint32_t* words = (uint32_t*)f.words.p;
   uint64_t* d_total = (uint64_t*)(words + kWordTotal);
   uint32_t* srx = (uint32_t*)f.dkw[0].p;
   uint32_t* sry = (uint32_t*)f.dkw[1].p;
@@ -638,9 +659,11 @@ gs_status forward_stages(Ctx* ctx, Frame& f, const ParamsDev& pd, hipStream_t s,
   const uint32_t* d_K = nullptr;   // device record count (device-count pipelines)
   uint32_t* overflow = nullptr;
   if (cap == 0) {
-    GS_HIP(hipMemcpyAsync(f.pinned, d_total, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+    // words 8..11: the record total and the visible count, in one readback
+    GS_HIP(hipMemcpyAsync(f.pinned, d_total, 2 * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
     GS_HIP(hipStreamSynchronize(s));
     const uint64_t K = f.pinned[0];
+    f.visible = (int64_t)(uint32_t)f.pinned[1];
     if (K >= 0xffffffffULL) {
       set_error("gs_render_fwd: %llu (Gaussian, tile) records exceed 2^32 - 1",
                 (unsigned long long)K);
@@ -649,8 +672,8 @@ gs_status forward_stages(Ctx* ctx, Frame& f, const ParamsDev& pd, hipStream_t s,
     f.K = (int64_t)K;
     n_rec = (uint32_t)K;
     for (int k = 0; k < 2; ++k) {
-      st = buf_ensure(ctx, f.tkey[k], (size_t)(K + 1) * 4);
-      if (st == GS_OK) st = buf_ensure(ctx, f.tval[k], (size_t)(K + 1) * 4);
+      st = buf_ensure(ctx, f.tkey[k], (size_t)(K + 1) * 4, s, f.last_use);
+      if (st == GS_OK) st = buf_ensure(ctx, f.tval[k], (size_t)(K + 1) * 4, s, f.last_use);
       if (st != GS_OK) return st;
     }
   } else {
@@ -736,13 +759,28 @@ gs_status gs_loss_grad(gs_ctx* ctx, const float* const* rendered, const float* c
   }
   gs_status st = set_device(ctx);
   if (st != GS_OK) return st;
-  StageTimer tm(ctx, ST_LOSS, (hipStream_t)stream);
-  return launch_loss(ctx, rendered, target, W, H, n_views, lambda_dssim, loss_out, dl_dimg,
-                     (hipStream_t)stream);
+  hipStream_t s = (hipStream_t)stream;
+  if (ctx->loss_scratch == nullptr) {
+    ctx->loss_scratch = new (std::nothrow) LossScratch();
+    if (ctx->loss_scratch == nullptr) {
+      set_error("gs_loss_grad: out of host memory");
+      return GS_ERR_NOMEM;
+    }
+  }
+  LossScratch& ls = *ctx->loss_scratch;
+  st = loss_reserve(ctx, ls, W, H, n_views, s);
+  if (st != GS_OK) return st;
+  {
+    StageTimer tm(ctx, ST_LOSS, s);
+    st = launch_loss(ls, rendered, target, W, H, n_views, lambda_dssim, loss_out, dl_dimg, s);
+  }
+  if (st != GS_OK) return st;
+  GS_HIP(hipEventRecord(ls.last_use, s));
+  return GS_OK;
 }
 
 gs_status gs_render_bwd(gs_ctx* ctx, gs_frame* frame, gs_params params,
-                        const float* const* dl_dimg, gs_params grads, int32_t accumulate,
+                        const float* const* dl_dimg, gs_params grads, int32_t flags,
                         void* stream) {
   if (ctx == nullptr || frame == nullptr || dl_dimg == nullptr) {
     set_error("gs_render_bwd: null argument");
@@ -760,7 +798,16 @@ gs_status gs_render_bwd(gs_ctx* ctx, gs_frame* frame, gs_params params,
     set_error("gs_render_bwd: parameter shapes differ from the frame's forward pass");
     return GS_ERR_INVALID;
   }
+  if ((flags & ~(GS_BWD_ACCUMULATE | GS_BWD_KEEP_SCREEN)) != 0) {
+    set_error("gs_render_bwd: unknown flags 0x%x", flags);
+    return GS_ERR_INVALID;
+  }
   Frame& f = *frame;
+  if (!f.acc_zeroed) {
+    set_error("gs_render_bwd: the frame's screen-space sums were kept by the previous backward; "
+              "run a forward first");
+    return GS_ERR_INVALID;
+  }
   for (int v = 0; v < f.views; ++v) {
     if (dl_dimg[v] == nullptr) {
       set_error("gs_render_bwd: dl_dimg[%d] is null", v);
@@ -771,7 +818,13 @@ gs_status gs_render_bwd(gs_ctx* ctx, gs_frame* frame, gs_params params,
   gs_status st = set_device(ctx);
   if (st != GS_OK) return st;
   hipStream_t s = (hipStream_t)stream;
-  return backward_stages(ctx, f, params_dev(params), grads_dev(grads, accumulate), s);
+  const GradsDev gd = grads_dev(grads, flags);
+  st = backward_stages(ctx, f, params_dev(params), gd, s);
+  if (st != GS_OK) return st;
+  // kept sums are cleared by the next forward
+  if (gd.keep_screen) f.acc_zeroed = false;
+  GS_HIP(hipEventRecord(f.last_use, s));
+  return GS_OK;
 }
 
 gs_status gs_adam_step(gs_ctx* ctx, gs_params p, gs_params g, gs_params m, gs_params v,
@@ -852,7 +905,9 @@ gs_status gs_frame_export(gs_frame* frame, int32_t what, int32_t view, void* dst
       need = (size_t)f.K * 8;
       if (view != -1) break;
       if (bytes < need) break;
-      return launch_export_keys(f, (uint64_t*)dst, s);
+      st = launch_export_keys(f, (uint64_t*)dst, s);
+      if (st == GS_OK) GS_HIP(hipEventRecord(f.last_use, s));
+      return st;
     case GS_EXPORT_VALUES:
       need = (size_t)f.K * 4;
       src = f.tval[f.tkey_sel].p;
@@ -885,7 +940,9 @@ gs_status gs_frame_export(gs_frame* frame, int32_t what, int32_t view, void* dst
         set_error("gs_frame_export: screen gradients need a 16-byte aligned destination");
         return GS_ERR_INVALID;
       }
-      return launch_export_screen_grads(f, view, (float*)dst, s);
+      st = launch_export_screen_grads(f, view, (float*)dst, s);
+      if (st == GS_OK) GS_HIP(hipEventRecord(f.last_use, s));
+      return st;
     case GS_EXPORT_SPLATS:
       src = f.splat.p;
       need = (size_t)f.views * n * 48;
@@ -921,13 +978,18 @@ gs_status gs_frame_export(gs_frame* frame, int32_t what, int32_t view, void* dst
     return GS_ERR_INVALID;
   }
   GS_HIP(hipMemcpyAsync(dst, (const char*)src + off, need, hipMemcpyDeviceToDevice, s));
+  GS_HIP(hipEventRecord(f.last_use, s));
   return GS_OK;
 }
 
 void gs_frame_release(gs_frame* frame) {
   if (frame == nullptr) return;
   (void)hipSetDevice(frame->ctx->device);
-  (void)hipDeviceSynchronize();
+  // every call that enqueues work on the frame's buffers records last_use after it
+  if (frame->last_use != nullptr)
+    (void)hipEventSynchronize(frame->last_use);
+  else
+    (void)hipDeviceSynchronize();
   frame_delete(frame);
 }
 

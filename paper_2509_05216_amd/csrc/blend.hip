@@ -610,7 +610,11 @@ __device__ inline void bwd_tile(BwdSmem<TILE, DEPTH>& sm, const ViewTable& vt, i
       part[2 * kPart + j] *= -0.5f;
       part[3 * kPart + j] *= -1.f;
       part[4 * kPart + j] *= -0.5f;
-      part[5 * kPart + j] *= __builtin_amdgcn_rcpf(q.w);  // o >= 1/255: 1-ulp reciprocal
+      // a nonzero sum comes from contributing pairs, whose opacity is >= 1/255 (the
+      // alpha test), so the 1-ulp reciprocal is finite; a zero sum stays zero
+      // whatever the opacity (no 0 * inf at an opacity that underflowed to 0)
+      const float e5 = part[5 * kPart + j];
+      part[5 * kPart + j] = e5 != 0.f ? e5 * __builtin_amdgcn_rcpf(q.w) : 0.f;
     }
     __syncthreads();
     // then the atomics, (slot, component) interleaved: the six geometric sums

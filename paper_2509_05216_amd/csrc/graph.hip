@@ -34,6 +34,10 @@ struct gs_graph {
   hipGraphExec_t exec = nullptr;
   uint32_t* pinned = nullptr;  // copy of the frame's device words after a replay
   int64_t records = 0;
+  // the graph's own loss workspace: captured kernels hold its pointers, so it
+  // is sized before capture and never shared with eager calls or other graphs
+  LossScratch loss;
+  hipEvent_t done = nullptr;   // recorded after every replay
 };
 
 namespace isogs {
@@ -64,8 +68,8 @@ gs_status enqueue_step(gs_graph* g, hipStream_t s) {
   for (int v = 0; v < g->nv; ++v) f.vt.v[v].image = g->images[v];
   gs_status st = forward_stages(ctx, f, params_dev(d.params), s, g->cap);
   if (st != GS_OK) return st;
-  st = launch_loss(ctx, g->images, g->targets, g->W, g->H, g->nv, d.lambda_dssim, d.loss, g->dl,
-                   s);
+  st = launch_loss(g->loss, g->images, g->targets, g->W, g->H, g->nv, d.lambda_dssim, d.loss,
+                   g->dl, s);
   if (st != GS_OK) return st;
   for (int v = 0; v < g->nv; ++v) f.vt.v[v].dimg = g->dl[v];
   st = backward_stages(ctx, f, params_dev(d.params), grads_dev(d.grads, 0), s);
@@ -88,19 +92,24 @@ void drop_graph(gs_graph* g) {
 }
 
 // Size the record buffers and sort scratch for the capacity, then capture.
+// Buffers are replaced only after the last replay (event `done`), the frame's
+// last eager use and the capture stream have finished with them.
 gs_status reserve_and_capture(gs_graph* g) {
   Ctx* ctx = g->ctx;
   Frame& f = *g->frame;
+  GS_HIP(hipEventSynchronize(g->done));
+  const hipStream_t cs = g->cstream;
   for (int k = 0; k < 2; ++k) {
-    gs_status st = buf_ensure(ctx, f.tkey[k], ((size_t)g->cap + 1) * 4);
-    if (st == GS_OK) st = buf_ensure(ctx, f.tval[k], ((size_t)g->cap + 1) * 4);
+    gs_status st = buf_ensure(ctx, f.tkey[k], ((size_t)g->cap + 1) * 4, cs, f.last_use);
+    if (st == GS_OK) st = buf_ensure(ctx, f.tval[k], ((size_t)g->cap + 1) * 4, cs, f.last_use);
     if (st != GS_OK) return st;
   }
   const uint32_t vn = (uint32_t)((size_t)f.views * (size_t)f.n);
   const uint32_t most = std::max(std::max(g->cap, vn), (uint32_t)f.vt.total_tiles);
-  gs_status st = sort_reserve(ctx, f.ss, most);
+  gs_status st = sort_reserve(ctx, f.ss, most, cs);
+  if (st == GS_OK) st = loss_reserve(ctx, g->loss, g->W, g->H, g->nv, cs);
   if (st != GS_OK) return st;
-  GS_HIP(hipDeviceSynchronize());
+  GS_HIP(hipStreamSynchronize(cs));
   drop_graph(g);
   ctx->capturing = true;
   hipError_t e = hipStreamBeginCapture(g->cstream, hipStreamCaptureModeThreadLocal);
@@ -177,6 +186,8 @@ gs_status gs_step_graph_create(gs_ctx* ctx, const gs_step_desc* desc, gs_graph**
   hipError_t e = hipSetDevice(ctx->device);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&g->cstream, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipHostMalloc((void**)&g->pinned, kWordCount * 4, hipHostMallocDefault);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&g->done, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventRecord(g->done, g->cstream);
   if (e != hipSuccess) st = hip_fail(e, "gs_step_graph_create");
   // eager measuring pass: sizes every buffer and measures K
   if (st == GS_OK)
@@ -216,6 +227,8 @@ gs_status gs_step_graph_launch(gs_graph* g, void* stream) {
   hipStream_t s = (hipStream_t)stream;
   GS_HIP(hipGraphLaunch(g->exec, s));
   GS_HIP(hipMemcpyAsync(g->pinned, g->frame->words.p, kWordCount * 4, hipMemcpyDeviceToHost, s));
+  GS_HIP(hipEventRecord(g->done, s));
+  GS_HIP(hipEventRecord(g->frame->last_use, s));
   return GS_OK;
 }
 
@@ -226,7 +239,10 @@ gs_status gs_step_graph_sync(gs_graph* g, int32_t* overflowed, int64_t* records,
   }
   GS_HIP(hipSetDevice(g->ctx->device));
   GS_HIP(hipStreamSynchronize((hipStream_t)stream));
+  GS_HIP(hipEventSynchronize(g->done));
   const uint64_t total = *reinterpret_cast<const uint64_t*>(g->pinned + kWordTotal);
+  g->frame->K = (int64_t)std::min<uint64_t>(total, g->cap);
+  g->frame->visible = (int64_t)g->pinned[kWordVisible];
   const bool over = g->pinned[kWordOverflow] != 0u;
   g->records = (int64_t)total;
   if (records) *records = (int64_t)total;
@@ -272,6 +288,8 @@ void gs_step_graph_destroy(gs_graph* g) {
   (void)hipDeviceSynchronize();
   drop_graph(g);
   if (g->frame != nullptr) gs_frame_release(g->frame);
+  loss_scratch_free(g->ctx, g->loss);
+  if (g->done != nullptr) (void)hipEventDestroy(g->done);
   if (g->cstream != nullptr) (void)hipStreamDestroy(g->cstream);
   if (g->pinned != nullptr) (void)hipHostFree(g->pinned);
   Ctx* ctx = g->ctx;
@@ -295,8 +313,8 @@ gs_status gs_autotune(gs_ctx* ctx, gs_params params, const gs_camera* cams, int3
   size_t pix = 0;
   for (int v = 0; v < n_views; ++v) pix += (size_t)cams[v].width * cams[v].height;
   const size_t rows = 14 + (size_t)(params.sh_degree + 1) * (params.sh_degree + 1) * 3;
-  gs_status st = buf_ensure(ctx, img, pix * 3 * 4);
-  if (st == GS_OK) st = buf_ensure(ctx, grd, rows * (size_t)params.n * 4);
+  gs_status st = buf_ensure(ctx, img, pix * 3 * 4, s);
+  if (st == GS_OK) st = buf_ensure(ctx, grd, rows * (size_t)params.n * 4, s);
   if (st != GS_OK) {
     buf_free(ctx, img);
     buf_free(ctx, grd);

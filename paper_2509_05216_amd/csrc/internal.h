@@ -46,6 +46,7 @@ enum Word {
   kWordBC = 4,          // two floats: Adam 1/(1 - b1^t), 1/sqrt(1 - b2^t)
   kWordStep = 6,        // int64: Adam step of the next graph launch
   kWordTotal = 8,       // u64: record count from the scan
+  kWordVisible = 10,    // (view, Gaussian) entries touching at least one tile
   kWordCount = 16
 };
 
@@ -89,6 +90,7 @@ struct GradsDev {
   float* logits;
   float* sh;
   int accumulate;
+  int keep_screen;  // leave the screen-space accumulators for export (no clearing)
 };
 
 __host__ __device__ inline int view_of_tile(const ViewTable& vt, int gt) {
@@ -122,7 +124,12 @@ struct DevBuf {
   size_t cap = 0;
 };
 
-gs_status buf_ensure(Ctx* ctx, DevBuf& b, size_t bytes);
+// Grows b to at least `bytes`.  A buffer that has to be replaced may still be
+// read by work queued earlier: the work enqueued on stream s, and the work
+// before event `prior` (optional, e.g. a frame's last use on another stream).
+// Both are waited for before the old buffer is freed; nothing else on the
+// device is (so the streams of other frames keep running).
+gs_status buf_ensure(Ctx* ctx, DevBuf& b, size_t bytes, hipStream_t s, hipEvent_t prior = nullptr);
 void buf_free(Ctx* ctx, DevBuf& b);
 
 // Pipeline stages timed with HIP events when a context enables timing.
@@ -144,7 +151,7 @@ struct Ctx {
   std::mutex mem_mutex;  // guards in_use / peak (render server workers share a context)
   int cu_count = 0;
   hipDeviceProp_t prop;
-  void* loss_scratch = nullptr;  // loss.hip workspace (g maps, block partials)
+  struct LossScratch* loss_scratch = nullptr;  // workspace of eager gs_loss_grad calls
   // set while a graph is being captured: no allocation, no stage events
   bool capturing = false;
   // stage timing
@@ -164,7 +171,21 @@ struct Ctx {
 
 void ctx_retain(Ctx* ctx);
 void ctx_release(Ctx* ctx);
-void free_loss_scratch(Ctx* ctx);
+
+// Workspace of the loss kernels: per-pixel SSIM partial derivatives of one view
+// (9 floats per pixel) and per-block loss partials.  The context holds one for
+// eager calls; every step graph holds its own, sized before capture, so a later
+// eager call that needs more room never frees memory a graph replays into.
+struct LossScratch {
+  DevBuf gmap, part;
+  hipEvent_t last_use = nullptr;  // recorded after each eager use
+};
+// Bytes of the two workspace arrays for views of these sizes.
+void loss_scratch_bytes(const int* W, const int* H, int nv, size_t* gmap_bytes,
+                        size_t* part_bytes);
+gs_status loss_reserve(Ctx* ctx, LossScratch& ls, const int* W, const int* H, int nv,
+                       hipStream_t s);
+void loss_scratch_free(Ctx* ctx, LossScratch& ls);
 
 // Records HIP events around a stage on stream s when the context times stages.
 struct StageTimer {
@@ -182,6 +203,7 @@ struct SortScratch {
   DevBuf hist;      // u32[256 * blocks]
   DevBuf partial;   // u64[blocks]
   DevBuf total;     // u64[1]
+  hipEvent_t prior = nullptr;  // last use of the owning frame (see buf_ensure)
 };
 
 struct Frame {
@@ -207,13 +229,16 @@ struct Frame {
   DevBuf words;                       // kWordCount device words
   DevBuf okey[2], oval[2];            // tile-order sort buffers
   SortScratch ss;
-  uint64_t* pinned = nullptr;  // host-pinned readback word
+  uint64_t* pinned = nullptr;  // host-pinned readback words (K, visible count)
+  // recorded on the call's stream after each call that enqueues work on the
+  // frame's buffers; a later call that must replace a buffer waits for it
+  hipEvent_t last_use = nullptr;
   size_t bytes() const;
 };
 
 // ------------------------------------------------------------- pipelines (api.hip)
 ParamsDev params_dev(const gs_params& p);
-GradsDev grads_dev(const gs_params& g, int accumulate);
+GradsDev grads_dev(const gs_params& g, int flags);
 gs_status forward_stages(Ctx* ctx, Frame& f, const ParamsDev& pd, hipStream_t s, uint32_t cap);
 gs_status backward_stages(Ctx* ctx, Frame& f, const ParamsDev& pd, const GradsDev& g,
                           hipStream_t s);
@@ -240,7 +265,7 @@ gs_status scan_tile_counts(Ctx* ctx, SortScratch& ss, const uint32_t* sidx, cons
                            uint32_t n, uint32_t* offs, uint32_t* srx, uint32_t* sry,
                            uint64_t* d_total, hipStream_t s);
 // Scratch for sorts of up to n pairs (so that no allocation happens later, e.g. in capture).
-gs_status sort_reserve(Ctx* ctx, SortScratch& ss, uint32_t n);
+gs_status sort_reserve(Ctx* ctx, SortScratch& ss, uint32_t n, hipStream_t s);
 // K = min(*total, cap); *overflow |= (*total > cap).
 gs_status launch_clamp_count(const uint64_t* total, uint32_t cap, uint32_t* K,
                              uint32_t* overflow, hipStream_t s);
@@ -253,6 +278,9 @@ gs_status launch_ranges(Frame& f, uint32_t n_rec, const uint32_t* d_K, hipStream
 // Tiles in descending list length (ties by tile id) for the persistent queue.
 gs_status launch_tile_order(Frame& f, hipStream_t s);
 gs_status launch_fill_u32(void* p, uint32_t value, size_t count, hipStream_t s);
+// After a depth sort of n keys (untouched entries keyed 0xffffffff): the count of
+// touched entries, read from the last pass's scanned digit table, into *dst.
+gs_status launch_visible_count(const SortScratch& ss, uint32_t n, uint32_t* dst, hipStream_t s);
 gs_status launch_export_keys(Frame& f, uint64_t* dst, hipStream_t s);
 // blend.hip
 gs_status launch_blend_fwd(const ViewTable& vt, Frame& f, hipStream_t s);
@@ -261,9 +289,10 @@ gs_status launch_blend_bwd(const ViewTable& vt, Frame& f, hipStream_t s);
 // float[.][n][12]: the six geometric sums, the three colour sums, 3 zero pads.
 gs_status launch_export_screen_grads(Frame& f, int view, float* dst, hipStream_t s);
 // loss.hip
-gs_status launch_loss(Ctx* ctx, const float* const* x, const float* const* y, const int* W,
-                      const int* H, int nv, float lambda, float* loss_out, float* const* dl,
-                      hipStream_t s);
+// The workspace must have been reserved for these sizes (loss_reserve).
+gs_status launch_loss(const LossScratch& ls, const float* const* x, const float* const* y,
+                      const int* W, const int* H, int nv, float lambda, float* loss_out,
+                      float* const* dl, hipStream_t s);
 // probe.hip
 gs_status launch_copy_probe(Ctx* ctx, const void* src, void* dst, size_t bytes, hipStream_t s);
 // adam.hip

@@ -376,18 +376,32 @@ __global__ __launch_bounds__(256) void k_loss_final(const double* __restrict__ p
 
 }  // namespace
 
-struct LossScratch {
-  DevBuf gmap, part;
-};
-
-// One scratch per context, kept for the context's lifetime.
-static LossScratch& loss_scratch(Ctx* ctx) {
-  return *reinterpret_cast<LossScratch*>(ctx->loss_scratch);
+void loss_scratch_bytes(const int* W, const int* H, int nv, size_t* gmap_bytes,
+                        size_t* part_bytes) {
+  size_t max_plane = 0, total_blocks = 0;
+  for (int v = 0; v < nv; ++v) {
+    const size_t plane = (size_t)W[v] * H[v];
+    if (plane > max_plane) max_plane = plane;
+    total_blocks += (size_t)((W[v] + kT - 1) / kT) * ((H[v] + kT - 1) / kT) * 3;
+  }
+  *gmap_bytes = sizeof(float) * 9 * max_plane;
+  *part_bytes = sizeof(double) * 2 * (total_blocks + kRedBlocks * kMaxViews);
 }
 
-gs_status launch_loss(Ctx* ctx, const float* const* x, const float* const* y, const int* W,
-                      const int* H, int nv, float lambda, float* loss_out, float* const* dl,
-                      hipStream_t s) {
+gs_status loss_reserve(Ctx* ctx, LossScratch& ls, const int* W, const int* H, int nv,
+                       hipStream_t s) {
+  if (ls.last_use == nullptr)
+    GS_HIP(hipEventCreateWithFlags(&ls.last_use, hipEventDisableTiming));
+  size_t gb = 0, pb = 0;
+  loss_scratch_bytes(W, H, nv, &gb, &pb);
+  gs_status st = buf_ensure(ctx, ls.gmap, gb, s, ls.last_use);
+  if (st != GS_OK) return st;
+  return buf_ensure(ctx, ls.part, pb, s, ls.last_use);
+}
+
+gs_status launch_loss(const LossScratch& ls, const float* const* x, const float* const* y,
+                      const int* W, const int* H, int nv, float lambda, float* loss_out,
+                      float* const* dl, hipStream_t s) {
   Win win;
   {
     double g[kN], sum = 0.0;
@@ -398,24 +412,26 @@ gs_status launch_loss(Ctx* ctx, const float* const* x, const float* const* y, co
     }
     for (int i = 0; i < kN; ++i) win.w[i] = (float)(g[i] / sum);
   }
-  if (ctx->loss_scratch == nullptr) ctx->loss_scratch = new LossScratch();
-  LossScratch& ls = loss_scratch(ctx);
-  size_t max_plane = 0, total_blocks = 0;
+  size_t total_blocks = 0;
   LossRed lr;
   lr.nv = nv;
   for (int v = 0; v < nv; ++v) {
     const size_t plane = (size_t)W[v] * H[v];
-    if (plane > max_plane) max_plane = plane;
     const int nbx = (W[v] + kT - 1) / kT, nby = (H[v] + kT - 1) / kT;
     lr.nblk[v] = nbx * nby * 3;
     lr.off[v] = (long long)total_blocks;
     lr.inv_count[v] = 1.0 / (3.0 * (double)plane);
     total_blocks += (size_t)lr.nblk[v];
   }
-  gs_status st = buf_ensure(ctx, ls.gmap, sizeof(float) * 9 * max_plane);
-  if (st != GS_OK) return st;
-  st = buf_ensure(ctx, ls.part, sizeof(double) * 2 * (total_blocks + kRedBlocks * kMaxViews));
-  if (st != GS_OK) return st;
+  {
+    size_t gb = 0, pb = 0;
+    loss_scratch_bytes(W, H, nv, &gb, &pb);
+    if (ls.gmap.cap < gb || ls.part.cap < pb) {
+      set_error("internal: loss workspace of %zu / %zu bytes is smaller than %zu / %zu",
+                ls.gmap.cap, ls.part.cap, gb, pb);
+      return GS_ERR_CAPACITY;
+    }
+  }
   double* part2 = (double*)ls.part.p + 2 * total_blocks;
   for (int v = 0; v < nv; ++v) {
     const dim3 grid((W[v] + kT - 1) / kT, (H[v] + kT - 1) / kT, 3);
@@ -440,13 +456,11 @@ gs_status launch_loss(Ctx* ctx, const float* const* x, const float* const* y, co
   return GS_OK;
 }
 
-void free_loss_scratch(Ctx* ctx) {
-  if (ctx->loss_scratch == nullptr) return;
-  LossScratch* ls = reinterpret_cast<LossScratch*>(ctx->loss_scratch);
-  buf_free(ctx, ls->gmap);
-  buf_free(ctx, ls->part);
-  delete ls;
-  ctx->loss_scratch = nullptr;
+void loss_scratch_free(Ctx* ctx, LossScratch& ls) {
+  buf_free(ctx, ls.gmap);
+  buf_free(ctx, ls.part);
+  if (ls.last_use != nullptr) (void)hipEventDestroy(ls.last_use);
+  ls.last_use = nullptr;
 }
 
 }  // namespace isogs

@@ -468,8 +468,10 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd_geom(ParamsDev prm, View
     if (a0.x == 0.f && a0.y == 0.f && a0.z == 0.f && a0.w == 0.f && a1.x == 0.f && a1.y == 0.f)
       continue;
     // leave the accumulator cleared for the next backward pass
-    a[0] = make_float4(0.f, 0.f, 0.f, 0.f);
-    a[1] = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (!gout.keep_screen) {
+      a[0] = make_float4(0.f, 0.f, 0.f, 0.f);
+      a[1] = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
     if (!loaded) {
       geom_body(prm, i, mu, Sig);
       loaded = true;
@@ -520,14 +522,16 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd_one(ParamsDev prm, ViewT
     col = c0.x != 0.f || c0.y != 0.f || c0.z != 0.f;
     const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
     if (geo) {  // leave the accumulators cleared for the next backward pass
-      a[0] = zero4;
-      a[1] = zero4;
+      if (!gout.keep_screen) {
+        a[0] = zero4;
+        a[1] = zero4;
+      }
       float mu[3], Sig[9];
       geom_body(prm, i, mu, Sig);
       geom_view(mu, Sig, vt.v[0], a0, a1, g_mu, Gs, g_op);
     }
     if (col) {
-      ac[0] = zero4;
+      if (!gout.keep_screen) ac[0] = zero4;
       const uint32_t mask = clampm[i];
       gr[0] = (mask & 1u) ? 0.f : c0.x;
       gr[1] = (mask & 2u) ? 0.f : c0.y;
@@ -697,7 +701,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     const bool col = a0.x != 0.f || a0.y != 0.f || a0.z != 0.f;
     if (__builtin_amdgcn_ballot_w64(col) == 0) continue;  // no lane of the wave has work
     if (col) {
-      acc4[(size_t)v * n + i] = make_float4(0.f, 0.f, 0.f, 0.f);  // cleared for the next pass
+      // cleared for the next pass
+      if (!gout.keep_screen) acc4[(size_t)v * n + i] = make_float4(0.f, 0.f, 0.f, 0.f);
       any_col = true;
     }
     const float gr0 = (col && !(mask & 1u)) ? a0.x : 0.f;

@@ -95,6 +95,7 @@ void worker_main(gs_server* sv, int slot_id) {
   (void)hipSetDevice(sv->ctx->device);
   for (;;) {
     std::vector<Request> batch;
+    gs_params scene_params;  // copied under the lock: add_scene may grow the vector
     size_t need = 0;
     {
       std::unique_lock<std::mutex> lk(sv->mu);
@@ -120,6 +121,7 @@ void worker_main(gs_server* sv, int slot_id) {
               sv->pending.erase(it);
             }
             batch = std::move(cand);
+            scene_params = sv->scenes[scene];
             slot.reserved = std::max(need, slot.bytes);
             sv->ledger = sv->ledger - held + slot.reserved;
             sv->peak_ledger = std::max(sv->peak_ledger, sv->ledger);
@@ -134,14 +136,13 @@ void worker_main(gs_server* sv, int slot_id) {
       }
     }
     // render the batch on this slot's stream
-    const int scene = batch.front().scene;
     gs_camera cams[kMaxViews];
     float* images[kMaxViews];
     for (size_t i = 0; i < batch.size(); ++i) {
       cams[i] = batch[i].cam;
       images[i] = batch[i].out;
     }
-    gs_status st = gs_render_fwd(sv->ctx, sv->scenes[scene], cams, (int32_t)batch.size(), images,
+    gs_status st = gs_render_fwd(sv->ctx, scene_params, cams, (int32_t)batch.size(), images,
                                  &sv->opts.render, &slot.frame, slot.stream);
     if (st == GS_OK && hipStreamSynchronize(slot.stream) != hipSuccess)
       st = hip_fail(hipErrorUnknown, "server batch");

@@ -474,6 +474,16 @@ __global__ __launch_bounds__(256) void k_export_keys(const uint32_t* __restrict_
 
 inline uint32_t nblocks_of(uint32_t n) { return (n + kChunk - 1) / kChunk; }
 
+// The scanned digit table of a sort's last pass holds, at (digit d, chunk 0),
+// the number of keys whose top byte is below d.  After a depth sort (positive
+// float32 depths, untouched entries keyed 0xffffffff) the entry of digit 0xff
+// is the count of touched entries; an empty table (every key below 0xff) gives n.
+__global__ void k_visible_count(const uint32_t* __restrict__ hist_scanned, uint32_t nblocks,
+                                uint32_t n, uint32_t* __restrict__ dst) {
+  const uint32_t below = hist_scanned[(size_t)255 * nblocks];
+  *dst = below <= n ? below : n;
+}
+
 }  // namespace
 
 gs_status launch_fill_u32(void* p, uint32_t value, size_t count, hipStream_t s) {
@@ -486,19 +496,20 @@ gs_status launch_fill_u32(void* p, uint32_t value, size_t count, hipStream_t s) 
   return GS_OK;
 }
 
-static gs_status ensure_scratch(Ctx* ctx, SortScratch& ss, uint32_t nb, size_t hist_entries) {
-  gs_status st = buf_ensure(ctx, ss.partial, sizeof(uint64_t) * (size_t)(nb + 1));
+static gs_status ensure_scratch(Ctx* ctx, SortScratch& ss, uint32_t nb, size_t hist_entries,
+                                hipStream_t s) {
+  gs_status st = buf_ensure(ctx, ss.partial, sizeof(uint64_t) * (size_t)(nb + 1), s, ss.prior);
   if (st != GS_OK) return st;
-  st = buf_ensure(ctx, ss.total, sizeof(uint64_t) * 2);
+  st = buf_ensure(ctx, ss.total, sizeof(uint64_t) * 2, s, ss.prior);
   if (st != GS_OK) return st;
-  return buf_ensure(ctx, ss.hist, sizeof(uint32_t) * (hist_entries + 1));
+  return buf_ensure(ctx, ss.hist, sizeof(uint32_t) * (hist_entries + 1), s, ss.prior);
 }
 
 gs_status scan_tile_counts(Ctx* ctx, SortScratch& ss, const uint32_t* sidx, const uint2* rect,
                            uint32_t n, uint32_t* offs, uint32_t* srx, uint32_t* sry,
                            uint64_t* d_total, hipStream_t s) {
   const uint32_t nb = nblocks_of(n);
-  gs_status st = ensure_scratch(ctx, ss, nb, 0);
+  gs_status st = ensure_scratch(ctx, ss, nb, 0, s);
   if (st != GS_OK) return st;
   // gather the counts once (random rect reads), then scan them in place, coalesced
   hipLaunchKernelGGL(k_counts, dim3((n + 255) / 256), dim3(256), 0, s, sidx, rect, n, offs, srx,
@@ -522,7 +533,7 @@ gs_status sort_pairs_u32(Ctx* ctx, SortScratch& ss, const uint32_t* kin, const u
   const uint32_t nb = nblocks_of(n);
   const uint32_t hist_n = (uint32_t)kRadix * nb;
   const uint32_t hb = nblocks_of(hist_n);
-  gs_status st = ensure_scratch(ctx, ss, hb > nb ? hb : nb, hist_n);
+  gs_status st = ensure_scratch(ctx, ss, hb > nb ? hb : nb, hist_n, s);
   if (st != GS_OK) return st;
   auto* hist = (uint32_t*)ss.hist.p;
   auto* partial = (uint64_t*)ss.partial.p;
@@ -581,18 +592,26 @@ gs_status launch_clamp_count(const uint64_t* total, uint32_t cap, uint32_t* K,
   return GS_OK;
 }
 
-gs_status sort_reserve(Ctx* ctx, SortScratch& ss, uint32_t n) {
+gs_status sort_reserve(Ctx* ctx, SortScratch& ss, uint32_t n, hipStream_t s) {
   const uint32_t nb = nblocks_of(n);
   const uint32_t hist_n = (uint32_t)kRadix * nb;
   const uint32_t hb = nblocks_of(hist_n);
-  return ensure_scratch(ctx, ss, hb > nb ? hb : nb, hist_n);
+  return ensure_scratch(ctx, ss, hb > nb ? hb : nb, hist_n, s);
+}
+
+gs_status launch_visible_count(const SortScratch& ss, uint32_t n, uint32_t* dst, hipStream_t s) {
+  if (n == 0) return launch_fill_u32(dst, 0u, 1, s);
+  hipLaunchKernelGGL(k_visible_count, dim3(1), dim3(1), 0, s, (const uint32_t*)ss.hist.p,
+                     nblocks_of(n), n, dst);
+  GS_LAUNCHED("visible_count");
+  return GS_OK;
 }
 
 gs_status launch_tile_order(Frame& f, hipStream_t s) {
   const uint32_t tiles = (uint32_t)f.vt.total_tiles;
   for (int k = 0; k < 2; ++k) {
-    gs_status st = buf_ensure(f.ctx, f.okey[k], (size_t)tiles * 4);
-    if (st == GS_OK) st = buf_ensure(f.ctx, f.oval[k], (size_t)tiles * 4);
+    gs_status st = buf_ensure(f.ctx, f.okey[k], (size_t)tiles * 4, s, f.last_use);
+    if (st == GS_OK) st = buf_ensure(f.ctx, f.oval[k], (size_t)tiles * 4, s, f.last_use);
     if (st != GS_OK) return st;
   }
   // keys into okey[1]; the sort reads them and ping-pongs okey[0] <-> okey[1]

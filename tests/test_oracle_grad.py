@@ -12,10 +12,10 @@ from tests._util import make_params, rel_l2
 GROUPS = ("means", "log_scales", "quats", "opacity_logits", "sh")
 
 
-def _scene(n=120, W=64, H=56, deg=3, seed=11, logit_hi=1.5):
+def _scene(n=120, W=64, H=56, deg=3, seed=11, logit_hi=1.5, logit_lo=-2.0):
     rng = np.random.default_rng(seed)
     p = make_params(rng.uniform(-0.35, 0.35, (n, 3)), log_scales=rng.uniform(-3.6, -2.6, (3, n)),
-                    quats=rng.normal(size=(4, n)), logits=rng.uniform(-2.0, logit_hi, n),
+                    quats=rng.normal(size=(4, n)), logits=rng.uniform(logit_lo, logit_hi, n),
                     sh=rng.normal(0, 0.25, ((deg + 1) ** 2 * 3, n)), sh_degree=deg)
     p64 = {k: (v.astype(np.float64) if isinstance(v, np.ndarray) else v) for k, v in p.items()}
     cam = camera.to_float32(camera.orbit_cameras(5, 2.5, 60.0, W, H)[2])
@@ -209,3 +209,103 @@ def test_param_grads_match_torch_autograd():
         (img * torch.tensor(w)).sum().backward()
         for k in GROUPS:
             assert rel_l2(g[k], P[k].grad.numpy()) < 1e-9, (seed, k)
+
+
+def clamp_scene(seed, deg, n=20, W=96, H=80):
+    """Few large splats spread over the image with logits U(3, 7) (opacity
+    0.953 .. 0.999).  alpha = o G passes 0.99 only within about 0.14 sigma of a
+    centre, so the splats are large (sigma 10 .. 25 px) and few enough for
+    their centres to be seen: every seed yields tens of clamped pairs that
+    contribute."""
+    from tests._util import identity_camera
+    rng = np.random.default_rng(seed)
+    xyz = np.hstack([rng.uniform(-0.9, 0.9, (n, 2)), rng.uniform(2.2, 2.8, (n, 1))])
+    p = make_params(xyz, log_scales=rng.uniform(-1.5, -1.1, (3, n)), quats=rng.normal(size=(4, n)),
+                    logits=rng.uniform(3.0, 7.0, n), sh=rng.normal(0, 0.25, ((deg + 1) ** 2 * 3, n)),
+                    sh_degree=deg)
+    p64 = {k: (v.astype(np.float64) if isinstance(v, np.ndarray) else v) for k, v in p.items()}
+    return p64, identity_camera(W, H, 80.0), rng.normal(size=(3, H, W))
+
+
+def test_alpha_clamp_branch_matches_torch_autograd():
+    """R14: where opacity * G exceeds 0.99 the forward clamps alpha, so alpha has
+    zero derivative there.  With opacities up to 0.999 the clamped branch is
+    taken by contributing pairs, and the oracle's hand-written backward must
+    still equal autograd of the transcription (whose clamp, like the forward,
+    passes no gradient above 0.99)."""
+    torch = pytest.importorskip("torch")
+    for seed, deg, tile in ((31, 3, 16), (32, 1, 8), (33, 0, 32)):
+        p, cam, w = clamp_scene(seed, deg)
+        bg = (0.2, 0.1, 0.3)
+        fw = pipeline.forward_view(p, cam, tile, bg)
+        _, g = pipeline.backward_view(p, cam, fw, w, bg)
+        # the clamped branch is exercised: count contributing pairs with o G > 0.99
+        pr = fw["proj"]
+        keys, gids, ranges = fw["lists"]
+        W, H = cam["width"], cam["height"]
+        tx = (W + tile - 1) // tile
+        clamped = live = 0
+        for t in range(ranges.shape[0]):
+            gg = gids[ranges[t, 0]:ranges[t, 1]]
+            X, Y = blend.tile_pixels(t % tx, t // tx, tile, W, H)
+            r = blend.composite_tile(pr, gg, X + 0.5, Y + 0.5, bg)
+            if gg.size:
+                clamped += int((r["contrib"] & (r["a_raw"] > 0.99)).sum())
+                live += int(r["contrib"].sum())
+        assert clamped >= 20, (seed, clamped, live)
+        P = {k: torch.tensor(p[k], dtype=torch.float64, requires_grad=True) for k in GROUPS}
+        img = _torch_forward(torch, P, cam, fw, tile, bg)
+        assert np.allclose(img.detach().numpy(), fw["image"], atol=1e-12)
+        (img * torch.tensor(w)).sum().backward()
+        for k in GROUPS:
+            assert rel_l2(g[k], P[k].grad.numpy()) < 1e-9, (seed, k)
+
+
+def test_alpha_clamp_opacity_derivative_by_finite_differences():
+    """R14 by central differences: a Gaussian whose every contributing pair is
+    clamped at 0.99 has exactly zero opacity-logit gradient, and one with no
+    clamped pair has the FD derivative."""
+    from tests._util import identity_camera
+    cam = identity_camera(32, 32, 60.0)
+    # two Gaussians stacked on the optical axis: the front one very opaque
+    # (every pixel it reaches within one sigma is clamped), the back one not
+    p = make_params([[0.0, 0.0, 2.0], [0.01, 0.0, 2.5]],
+                    log_scales=np.full((3, 2), np.log(0.02)), logits=[8.0, 0.0],
+                    sh=[[0.6, 0.2], [0.3, 0.5], [0.1, 0.7]])
+    p = {k: (v.astype(np.float64) if isinstance(v, np.ndarray) else v) for k, v in p.items()}
+    w = np.random.default_rng(4).normal(size=(3, 32, 32))
+    fw = pipeline.forward_view(p, cam, 16)
+    _, g = pipeline.backward_view(p, cam, fw, w)
+
+    def L(logit0, logit1):
+        q = dict(p, opacity_logits=np.array([logit0, logit1]))
+        return float((pipeline.forward_view(q, cam, 16)["image"] * w).sum())
+
+    h = 1e-6
+    fd1 = (L(8.0, h) - L(8.0, -h)) / (2 * h)
+    assert abs(g["opacity_logits"][1] - fd1) <= 1e-6 * max(abs(fd1), 1e-3)
+    assert abs(fd1) > 1e-4
+    # front Gaussian: pixels with o G > 0.99 contribute nothing; the others do, so
+    # compare with FD (which sees the same clamp)
+    fd0 = (L(8.0 + h, 0.0) - L(8.0 - h, 0.0)) / (2 * h)
+    assert abs(g["opacity_logits"][0] - fd0) <= 1e-6 * max(abs(fd0), 1e-6)
+
+
+def test_underflowed_opacity_gets_zero_gradient():
+    """A logit so negative that the opacity is 0 in float32 (sigmoid(-120))
+    makes the Gaussian invisible: its every gradient is exactly zero, and the
+    other Gaussians' gradients are those of the scene without it."""
+    p, cam, w = _scene(n=40, seed=41)
+    p["opacity_logits"][7] = -120.0
+    fw = pipeline.forward_view(p, cam, 16)
+    _, g = pipeline.backward_view(p, cam, fw, w)
+    for k in GROUPS:
+        col = g[k][..., 7]
+        assert np.all(np.isfinite(g[k])) and np.all(col == 0), k
+    keep = np.array([i for i in range(40) if i != 7])
+    q = {k: (v[..., keep] if isinstance(v, np.ndarray) else v) for k, v in p.items()}
+    fq = pipeline.forward_view(q, cam, 16)
+    _, gq = pipeline.backward_view(q, cam, fq, w)
+    assert np.allclose(fw["image"], fq["image"], atol=1e-15)
+    for k in GROUPS:
+        assert np.allclose(g[k][..., keep], gq[k], rtol=1e-12, atol=1e-15), k

@@ -1,9 +1,12 @@
 """Pins of the oracle's initialisation: Philox4x32-10 known-answer vectors and
-distribution checks of the derived uniforms and normals."""
+distribution checks of the derived uniforms and normals (moments, and
+Kolmogorov-Smirnov tests against the uniform, normal, exponential and
+Rayleigh-angle laws the Box-Muller transform is defined to produce)."""
 import json
 import os
 
 import numpy as np
+import pytest
 
 from oracle import init
 
@@ -46,3 +49,38 @@ def test_init_rules():
     q = init.init_from_points(xyz, 0, log_scale_range=(-5, -3), seed=77)
     assert q["log_scales"].min() >= -5 and q["log_scales"].max() < -3
     assert np.all(q["quats"][0] == 1) and np.all(q["sh"] == 0)
+
+
+def test_uniform_and_box_muller_distributions_ks():
+    """Kolmogorov-Smirnov against the exact laws: u = (x >> 8) 2^-24 is uniform
+    on [0, 1); a Box-Muller pair (z0, z1) is two independent standard normals,
+    so z0^2 + z1^2 is exponential with mean 2 and atan2(z1, z0) is uniform on
+    (-pi, pi].  A wrong constant (2 pi, the factor -2, a swapped sine and
+    cosine with a sign, the 2^-24 scale) shifts one of these laws."""
+    stats = pytest.importorskip("scipy.stats")
+    n = 200_000
+    idx = np.arange(n, dtype=np.uint64)
+    z = np.zeros(n, np.uint64)
+    u = init.philox4x32_10([idx, z + 3, z, z], (12345, 678))
+    U = init.uniform24(u[0])
+    assert stats.kstest(U, "uniform").pvalue > 1e-3
+    a, b = init.box_muller(u[1], u[2])
+    for x in (a, b):
+        assert stats.kstest(x, "norm").pvalue > 1e-3
+    r2 = a * a + b * b
+    assert stats.kstest(r2, "expon", args=(0, 2.0)).pvalue > 1e-3
+    ang = np.arctan2(b, a)
+    assert stats.kstest(ang, "uniform", args=(-np.pi, 2 * np.pi)).pvalue > 1e-3
+    # independence of the pair: correlation of the two normals and of their squares
+    assert abs(np.corrcoef(a, b)[0, 1]) < 0.02
+    assert abs(np.corrcoef(a * a, b * b)[0, 1]) < 0.02
+
+
+def test_random_quaternions_uniform_on_the_sphere():
+    """Normalised 4-D normals are uniform on S^3: each coordinate q_k satisfies
+    q_k^2 ~ Beta(1/2, 3/2)."""
+    stats = pytest.importorskip("scipy.stats")
+    xyz = np.zeros((3, 50_000))
+    p = init.init_from_points(xyz, 0, random_quats=True, seed=99)
+    for k in range(4):
+        assert stats.kstest(p["quats"][k] ** 2, "beta", args=(0.5, 1.5)).pvalue > 1e-3, k

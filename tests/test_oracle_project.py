@@ -186,7 +186,12 @@ def test_sh_orthonormal():
     assert np.allclose(G, np.eye(16), atol=1e-12)
 
 
-def test_sh_matches_scipy_up_to_sign():
+def test_sh_matches_scipy_with_fixed_signs():
+    """Real SH with the Condon-Shortley phase kept (R9), from scipy's complex
+    harmonics Y_l^m (which carry that phase): sqrt(2) Im Y_l^|m| for m < 0,
+    Y_l^0 for m = 0 and sqrt(2) Re Y_l^m for m > 0.  Every basis function has
+    one fixed sign, so a sign slip in any of the sixteen polynomials fails
+    (orthonormality cannot see signs)."""
     sp = pytest.importorskip("scipy.special")
     d, _ = _sphere_quadrature(12, 24)
     theta = np.arccos(np.clip(d[2], -1, 1))
@@ -195,15 +200,27 @@ def test_sh_matches_scipy_up_to_sign():
     j = 0
     for l in range(4):
         for m in range(-l, l + 1):
+            c = sp.sph_harm_y(l, abs(m), theta, phi)
             if m == 0:
-                ref = sp.sph_harm_y(l, 0, theta, phi).real
+                ref = c.real
             elif m > 0:
-                ref = math.sqrt(2) * (-1) ** m * sp.sph_harm_y(l, m, theta, phi).real
+                ref = math.sqrt(2) * c.real
             else:
-                ref = math.sqrt(2) * (-1) ** m * sp.sph_harm_y(l, -m, theta, phi).imag
-            ok = np.allclose(Y[j], ref, atol=1e-12) or np.allclose(Y[j], -ref, atol=1e-12)
-            assert ok, (l, m)
+                ref = math.sqrt(2) * c.imag
+            assert np.allclose(Y[j], ref, atol=1e-12), (l, m)
             j += 1
+
+
+def test_sh_low_order_values_by_hand():
+    """Degree 0 and 1 at the axis directions, from the closed forms: Y_0 =
+    1/(2 sqrt(pi)); with the phase, (Y_1^-1, Y_1^0, Y_1^1) = sqrt(3/(4 pi)) (-y, z, -x)."""
+    k1 = math.sqrt(3.0 / (4.0 * math.pi))
+    dirs = np.eye(3)
+    Y = sh.basis(dirs, 1)
+    assert np.allclose(Y[0], 0.5 / math.sqrt(math.pi), rtol=1e-15)
+    assert np.allclose(Y[1:4, 0], [0.0, 0.0, -k1], atol=1e-16)   # d = +x
+    assert np.allclose(Y[1:4, 1], [-k1, 0.0, 0.0], atol=1e-16)   # d = +y
+    assert np.allclose(Y[1:4, 2], [0.0, k1, 0.0], atol=1e-16)    # d = +z
 
 
 def test_sh_gradient_matches_finite_differences():

@@ -145,48 +145,177 @@ def test_empty_and_single(P, ctx):
 
 
 # ------------------------------------------------------------------ backward
-def test_backward_matches_oracle(P, ctx):
-    scene = gsscenes.make_scene("iso1m", n=3000, G=96)
-    cams = _cams(4, 160, 128)[:2]
+def _oracle_grads(params, cams, fws, ws, bg=(0.0, 0.0, 0.0)):
+    total, accs = None, []
+    for c, f, w in zip(cams, fws, ws):
+        acc, g = pipeline.backward_view(params, c, f, w, bg)
+        accs.append(acc)
+        total = pipeline.add_grads(total, g)
+    return total, accs
+
+
+def _check_grads(gg, total, tol=1e-3):
+    for k in GROUPS:
+        if np.linalg.norm(total[k]) == 0:
+            assert np.abs(gg[k]).max() < 1e-9, k
+            continue
+        e = rel_l2(gg[k], total[k])
+        print(f"{k}: rel L2 {e:.2e}")
+        assert e < tol, (k, e)
+
+
+PL = 3  # persistent work-queue launch, longest tile first
+
+
+@pytest.mark.parametrize("tile,depth,flags", [
+    (8, 32, 0), (8, 64, 0), (8, 64, PL), (16, 32, 0), (16, 256, 0), (16, 256, PL),
+    (32, 64, 0), (32, 64, PL), (32, 256, 0), (32, 256, PL)])
+def test_backward_matches_oracle(P, ctx, tile, depth, flags):
+    """Parameter gradients of the compositing backward in every tile size, LDS
+    batch depth and launch form the autotuner can pick, against the oracle.
+    Lists run to several hundred records, so shallow depths take many LDS
+    batches; the views are ragged at every tile size."""
+    scene = gsscenes.make_scene("iso1m", n=5000, G=96)
+    sizes = [(160, 128), (100, 72)]
+    cams = [_cams(4, W, H)[i] for i, (W, H) in enumerate(sizes)]
     params = P.Params.from_numpy(scene.params)
     rng = np.random.default_rng(5)
-    ws = [rng.normal(size=(3, 128, 160)) for _ in cams]
-    imgs, frame = P.render_fwd(ctx, params, [P.camera_from_dict(c) for c in cams])
+    ws = [rng.normal(size=(3, H, W)) for W, H in sizes]
+    imgs, frame = P.render_fwd(ctx, params, [P.camera_from_dict(c) for c in cams], tile=tile,
+                               lds_depth=depth, flags=flags)
     dl = [torch.tensor(w, dtype=torch.float32, device="cuda") for w in ws]
     grads = P.render_bwd(ctx, frame, params, dl)
     torch.cuda.synchronize()
-    # the screen accumulators are cleared by the backward; re-run the blend
-    # backward alone through a fresh forward to read them is not needed: compare params
-    fws = _oracle_fw(scene.params, cams, 16)
-    total = None
-    for c, f, w in zip(cams, fws, ws):
-        acc, g = pipeline.backward_view(scene.params, c, f, w)
-        total = pipeline.add_grads(total, g)
-    gg = grads.to_numpy()
-    for k in GROUPS:
-        e = rel_l2(gg[k], total[k])
-        print(f"{k}: rel L2 {e:.2e}")
-        assert e < 1e-3, (k, e)
+    fws = _oracle_fw(scene.params, cams, tile)
+    longest = max(int(np.diff(f["lists"][2], axis=1).max()) for f in fws)
+    assert longest > 2 * depth, longest
+    total, _ = _oracle_grads(scene.params, cams, fws, ws)
+    _check_grads(grads.to_numpy(), total)
 
 
-def test_screen_space_accumulators(P, ctx):
-    """dL/d(mean2D, conic, opacity, rgb) per Gaussian (the blend backward alone)."""
-    scene = gsscenes.make_scene("tiny", n=2000)
-    cams = _cams(3, 128, 128)[:1]
+def test_screen_space_sums_match_oracle(P, ctx):
+    """dL/d(mean2D, conic, opacity, rgb) per (view, Gaussian) kept by the blend
+    backward (GS_BWD_KEEP_SCREEN) against the oracle's compositing derivative;
+    without the flag the library consumes and clears them."""
+    scene = gsscenes.make_scene("iso1m", n=3000, G=96)
+    cams = _cams(3, 128, 112)[:2]
+    n = 3000
     params = P.Params.from_numpy(scene.params)
-    w = np.random.default_rng(6).normal(size=(3, 128, 128))
-    imgs, frame = P.render_fwd(ctx, params, [P.camera_from_dict(c) for c in cams])
-    dl = [torch.tensor(w, dtype=torch.float32, device="cuda")]
-    grads = P.render_bwd(ctx, frame, params, dl)
+    rng = np.random.default_rng(6)
+    ws = [rng.normal(size=(3, 112, 128)) for _ in cams]
+    gcams = [P.camera_from_dict(c) for c in cams]
+    dl = [torch.tensor(w, dtype=torch.float32, device="cuda") for w in ws]
+    imgs, frame = P.render_fwd(ctx, params, gcams)
+    grads = P.render_bwd(ctx, frame, params, dl, keep_screen=True)
     torch.cuda.synchronize()
-    # after the pass the library clears its accumulators
-    acc_after = frame.export("screen_grads").cpu().numpy()
-    assert np.all(acc_after == 0)
-    f = _oracle_fw(scene.params, cams, 16)[0]
-    acc, g = pipeline.backward_view(scene.params, cams[0], f, w)
+    sg = frame.export("screen_grads").cpu().numpy().reshape(len(cams), n, 12)
+    with pytest.raises(P.IsogsError):      # kept sums: a second backward needs a forward
+        P.render_bwd(ctx, frame, params, dl)
+    fws = _oracle_fw(scene.params, cams, 16)
+    total, accs = _oracle_grads(scene.params, cams, fws, ws)
+    for v, acc in enumerate(accs):
+        want = {"m": acc["m"], "conic": acc["conic"], "opacity": acc["opacity"][None],
+                "rgb": acc["rgb"]}
+        got = {"m": sg[v, :, 0:2].T, "conic": sg[v, :, 2:5].T, "opacity": sg[v, :, 5][None],
+               "rgb": sg[v, :, 6:9].T}
+        for k in want:
+            e = rel_l2(got[k], want[k])
+            print(f"view {v} {k}: rel L2 {e:.2e}")
+            assert e < 1e-3, (v, k, e)
+        assert np.all(sg[v, :, 9:] == 0)
+    _check_grads(grads.to_numpy(), total)
+    # a forward clears the kept sums; the default backward consumes them
+    P.render_fwd(ctx, params, gcams, images=imgs, frame=frame)
+    grads2 = P.render_bwd(ctx, frame, params, dl)
+    torch.cuda.synchronize()
+    assert np.all(frame.export("screen_grads").cpu().numpy() == 0)
+    for a, b in zip(grads2.tensors(), grads.tensors()):
+        assert rel_l2(a.cpu().numpy(), b.cpu().numpy()) < 1e-5
+
+
+def _high_opacity(scene, seed):
+    """The scene's parameters with opacity logits U(3, 7) (opacity 0.953 .. 0.999):
+    alpha = o G passes the 0.99 clamp near the centres of most splats."""
+    p = dict(scene.params)
+    rng = np.random.default_rng(seed)
+    p["opacity_logits"] = rng.uniform(3.0, 7.0, p["means"].shape[1]).astype(np.float32)
+    return p
+
+
+@pytest.mark.parametrize("tile,flags", [(16, 0), (8, PL), (32, 0)])
+def test_alpha_clamp_high_opacity_matches_oracle(P, ctx, tile, flags):
+    """R14 on the device: with opacities up to 0.999 many contributing pairs are
+    clamped at alpha = 0.99, where alpha has zero derivative.  Images, and
+    parameter gradients from an upstream gradient that is zero at flagged
+    pixels, must match the oracle."""
+    from oracle import blend
+    from tests.test_oracle_grad import clamp_scene
+    cases = []
+    scene = gsscenes.make_scene("iso1m", n=3000, G=96)
+    p = _high_opacity(scene, 17)
+    cams = [_cams(4, W, H)[i] for i, (W, H) in enumerate([(160, 128), (96, 88)])]
+    cases.append((p, cams, (0.0, 0.0, 0.0)))
+    for seed, deg in ((31, 3), (32, 1)):
+        q, cam, _ = clamp_scene(seed, deg)
+        cases.append(({k: (v.astype(np.float32) if isinstance(v, np.ndarray) else v)
+                       for k, v in q.items()}, [cam], (0.2, 0.1, 0.3)))
+    for p, cams, bg in cases:
+        params = P.Params.from_numpy(p)
+        gcams = [P.camera_from_dict(c) for c in cams]
+        imgs, frame = P.render_fwd(ctx, params, gcams, tile=tile, flags=flags, bg=bg)
+        torch.cuda.synchronize()
+        fws = _oracle_fw(p, cams, tile, bg)
+        _check_binning(P, frame, fws, p["means"].shape[1])
+        clamped = 0
+        for v, f in enumerate(fws):
+            assert_image(f, imgs[v].cpu().numpy(), bg=bg)
+            pr = f["proj"]
+            _, gids, ranges = f["lists"]
+            tx = f["tiles"][0]
+            for t in range(ranges.shape[0]):
+                g = gids[ranges[t, 0]:ranges[t, 1]]
+                if g.size == 0:
+                    continue
+                X, Y = blend.tile_pixels(t % tx, t // tx, tile, pr["W"], pr["H"])
+                r = blend.composite_tile(pr, g, X + 0.5, Y + 0.5, bg)
+                clamped += int((r["contrib"] & (r["a_raw"] > 0.99)).sum())
+        assert clamped >= 20, clamped
+        rng = np.random.default_rng(8)
+        ws = [rng.normal(size=(3, c["height"], c["width"])) * ~f["flags"][None]
+              for c, f in zip(cams, fws)]
+        dl = [torch.tensor(w, dtype=torch.float32, device="cuda") for w in ws]
+        grads = P.render_bwd(ctx, frame, params, dl)
+        torch.cuda.synchronize()
+        total, _ = _oracle_grads(p, cams, fws, ws, bg)
+        _check_grads(grads.to_numpy(), total)
+        frame.release()
+
+
+def test_underflowed_opacity_gets_finite_zero_gradient(P, ctx):
+    """A Gaussian whose opacity is 0 in float32 (logit -120) contributes nothing:
+    its gradients are exactly zero and every gradient is finite."""
+    scene = gsscenes.make_scene("iso1m", n=2000, G=96)
+    p = dict(scene.params)
+    p["opacity_logits"] = p["opacity_logits"].copy()
+    cams = _cams(3, 128, 128)[:1]
+    fw0 = _oracle_fw(p, cams, 16)[0]
+    # a Gaussian that is listed in some tile
+    idx = int(fw0["lists"][1][len(fw0["lists"][1]) // 2])
+    p["opacity_logits"][idx] = -120.0
+    params = P.Params.from_numpy(p)
+    w = np.random.default_rng(9).normal(size=(3, 128, 128))
+    imgs, frame = P.render_fwd(ctx, params, [P.camera_from_dict(cams[0])])
+    grads = P.render_bwd(ctx, frame, params, [torch.tensor(w, dtype=torch.float32,
+                                                           device="cuda")])
+    torch.cuda.synchronize()
     gg = grads.to_numpy()
     for k in GROUPS:
-        assert rel_l2(gg[k], g[k]) < 1e-3, k
+        assert np.all(np.isfinite(gg[k])), k
+        assert np.all(gg[k][..., idx] == 0), k
+    fw = _oracle_fw(p, cams, 16)[0]
+    assert_image(fw, imgs[0].cpu().numpy())
+    total, _ = _oracle_grads(p, cams, [fw], [w])
+    _check_grads(gg, total)
 
 
 # ------------------------------------------------------------------ loss, adam

@@ -230,6 +230,23 @@ gs_status gs_loss_grad(gs_ctx* ctx, const float* const* rendered,
                        int32_t n_views, float lambda_dssim, float* loss_out,
                        float* const* dl_dimg, void* stream);
 
+/* gs_loss_grad without allocation, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, kernels and results as gs_loss_grad,
+ * but the workspace is a fixed device array of 39,337,984 bytes per GPU,
+ * held from the first context created on that GPU until the process ends:
+ * each view may hold at most 1,048,576 (2^20) pixels, e.g. 1024 x 1024; larger
+ * views return GS_ERR_CAPACITY before anything is launched.  The call
+ * allocates nothing (no hipMalloc, hipFree or event creation) and records no
+ * stage timing.  Every call on one GPU shares that array (its contents are
+ * whatever the last call left; nothing in it needs clearing between calls):
+ * calls that overlap on one GPU, on different streams or from different
+ * threads, race and give wrong results. */
+gs_status gs_loss_grad_noalloc(gs_ctx* ctx, const float* const* rendered,
+                               const float* const* target, const gs_camera* cams,
+                               int32_t n_views, float lambda_dssim, float* loss_out,
+                               float* const* dl_dimg, void* stream);
+
 /* Backward of gs_render_fwd for the frame's views (the gradient step of the
  * 3D-GS training adopted in Sec. III): reverse front-to-back traversal that
  * recomputes transmittance (no per-pixel lists are stored), then the chain

@@ -4,7 +4,7 @@ colour, tile binning and sort, alpha compositing, its backward, the loss
 gradient and Adam), behind the C ABI of include/isogs.h."""
 from ._lib import IsogsError, lib  # noqa: F401
 from .core import (Context, Frame, Params, adam_step, bw_probe, camera, camera_from_dict,  # noqa: F401
-                   camera_to_dict, init_from_points, loss_grad, orbit_cameras, render_bwd,
+                   camera_to_dict, init_from_points, loss_grad, loss_grad_into, orbit_cameras, render_bwd,
                    render_fwd)
 from .autograd import RasterizeFn, rasterize  # noqa: F401
 from .batched import StepGraph, autotune  # noqa: F401
@@ -12,5 +12,5 @@ from .serve import Server  # noqa: F401
 from .core import LONGEST_FIRST, PERSISTENT  # noqa: F401
 
 __all__ = ["Context", "Frame", "Params", "IsogsError", "adam_step", "camera",
-           "camera_from_dict", "camera_to_dict", "init_from_points", "loss_grad", "lib",
+           "camera_from_dict", "camera_to_dict", "init_from_points", "loss_grad", "loss_grad_into", "lib",
            "orbit_cameras", "render_bwd", "render_fwd", "RasterizeFn", "rasterize"]

@@ -114,6 +114,8 @@ SIGNATURES = [
                                 C.POINTER(GsRenderOpts), C.POINTER(_P), _P]),
     ("gs_loss_grad", C.c_int, [_P, _PP, _PP, C.POINTER(GsCamera), C.c_int32, C.c_float, _P,
                                _PP, _P]),
+    ("gs_loss_grad_noalloc", C.c_int, [_P, _PP, _PP, C.POINTER(GsCamera), C.c_int32,
+                                       C.c_float, _P, _PP, _P]),
     ("gs_render_bwd", C.c_int, [_P, _P, GsParams, _PP, GsParams, C.c_int32, _P]),
     ("gs_adam_step", C.c_int, [_P, GsParams, GsParams, GsParams, GsParams,
                                C.POINTER(GsAdamOpts), C.c_int64, _P]),

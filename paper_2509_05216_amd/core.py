@@ -246,12 +246,25 @@ def loss_grad(ctx, rendered, targets, cams, lam=0.2, *, want_grad=True, stream=N
     dev = rendered[0].device
     loss = torch.empty(1, dtype=torch.float32, device=dev)
     grads = [torch.empty_like(r) for r in rendered] if want_grad else None
-    ra, k1 = L.ptr_array([r.data_ptr() for r in rendered])
-    ta, k2 = L.ptr_array([t.contiguous().data_ptr() for t in targets])
-    ga, k3 = (L.ptr_array([g.data_ptr() for g in grads]) if want_grad else (None, None))
-    L.check(L.lib().gs_loss_grad(ctx.handle, ra, ta, _cam_array(cams), len(cams), float(lam),
-                                 _ptr(loss), ga, _stream(stream)))
+    loss_grad_into(ctx, rendered, [t.contiguous() for t in targets], cams, loss, grads, lam,
+                   stream=stream)
     return loss, grads
+
+
+def loss_grad_into(ctx, rendered, targets, cams, loss, grads, lam=0.2, *, noalloc=False,
+                   stream=None):
+    """Loss and image gradients into caller tensors (loss: float32 (1,), grads: a list
+    like `rendered`, or None).  noalloc=True calls gs_loss_grad_noalloc, whose
+    workspace is a fixed device array (views of at most 2^20 pixels)."""
+    for t in targets:
+        if not t.is_contiguous():
+            raise ValueError("target tensors must be contiguous")
+    ra, k1 = L.ptr_array([r.data_ptr() for r in rendered])
+    ta, k2 = L.ptr_array([t.data_ptr() for t in targets])
+    ga, k3 = (L.ptr_array([g.data_ptr() for g in grads]) if grads is not None else (None, None))
+    fn = L.lib().gs_loss_grad_noalloc if noalloc else L.lib().gs_loss_grad
+    L.check(fn(ctx.handle, ra, ta, _cam_array(cams), len(cams), float(lam),
+               _ptr(loss) if loss is not None else None, ga, _stream(stream)))
 
 
 BWD_ACCUMULATE = 1

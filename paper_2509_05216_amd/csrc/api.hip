@@ -398,6 +398,12 @@ gs_status gs_ctx_create(int device, size_t mem_budget, gs_ctx** out) {
     return GS_ERR_UNSUPPORTED;
   }
   c->cu_count = c->prop.multiProcessorCount;
+  // address of this device's fixed loss workspace (gs_loss_grad_noalloc)
+  const gs_status ws = loss_noalloc_setup(device);
+  if (ws != GS_OK) {
+    delete c;
+    return ws;
+  }
   *out = c;
   return GS_OK;
 }
@@ -728,6 +734,35 @@ gs_status backward_stages(Ctx* ctx, Frame& f, const ParamsDev& pd, const GradsDe
   return launch_preprocess_bwd(pd, f.vt, f, g, s);
 }
 
+// Arguments shared by gs_loss_grad and gs_loss_grad_noalloc: checks them and
+// fills the view sizes.
+static gs_status loss_args(const char* what, gs_ctx* ctx, const float* const* rendered,
+                           const float* const* target, const gs_camera* cams, int32_t n_views,
+                           float lambda_dssim, int* W, int* H) {
+  if (ctx == nullptr || rendered == nullptr || target == nullptr || cams == nullptr) {
+    set_error("%s: null argument", what);
+    return GS_ERR_INVALID;
+  }
+  if (n_views < 1 || n_views > kMaxViews) {
+    set_error("%s: n_views %d not in [1, %d]", what, n_views, kMaxViews);
+    return GS_ERR_INVALID;
+  }
+  if (!(lambda_dssim >= 0.f && lambda_dssim <= 1.f)) {
+    set_error("%s: lambda %g not in [0, 1]", what, (double)lambda_dssim);
+    return GS_ERR_INVALID;
+  }
+  for (int v = 0; v < n_views; ++v) {
+    if (!valid_camera(cams[v], v)) return GS_ERR_INVALID;
+    if (rendered[v] == nullptr || target[v] == nullptr) {
+      set_error("%s: image pointer of view %d is null", what, v);
+      return GS_ERR_INVALID;
+    }
+    W[v] = cams[v].width;
+    H[v] = cams[v].height;
+  }
+  return GS_OK;
+}
+
 }  // namespace isogs
 
 extern "C" {
@@ -735,29 +770,11 @@ extern "C" {
 gs_status gs_loss_grad(gs_ctx* ctx, const float* const* rendered, const float* const* target,
                        const gs_camera* cams, int32_t n_views, float lambda_dssim,
                        float* loss_out, float* const* dl_dimg, void* stream) {
-  if (ctx == nullptr || rendered == nullptr || target == nullptr || cams == nullptr) {
-    set_error("gs_loss_grad: null argument");
-    return GS_ERR_INVALID;
-  }
-  if (n_views < 1 || n_views > kMaxViews) {
-    set_error("gs_loss_grad: n_views %d not in [1, %d]", n_views, kMaxViews);
-    return GS_ERR_INVALID;
-  }
-  if (!(lambda_dssim >= 0.f && lambda_dssim <= 1.f)) {
-    set_error("gs_loss_grad: lambda %g not in [0, 1]", (double)lambda_dssim);
-    return GS_ERR_INVALID;
-  }
   int W[kMaxViews], H[kMaxViews];
-  for (int v = 0; v < n_views; ++v) {
-    if (!valid_camera(cams[v], v)) return GS_ERR_INVALID;
-    if (rendered[v] == nullptr || target[v] == nullptr) {
-      set_error("gs_loss_grad: image pointer of view %d is null", v);
-      return GS_ERR_INVALID;
-    }
-    W[v] = cams[v].width;
-    H[v] = cams[v].height;
-  }
-  gs_status st = set_device(ctx);
+  gs_status st = loss_args("gs_loss_grad", ctx, rendered, target, cams, n_views, lambda_dssim,
+                           W, H);
+  if (st != GS_OK) return st;
+  st = set_device(ctx);
   if (st != GS_OK) return st;
   hipStream_t s = (hipStream_t)stream;
   if (ctx->loss_scratch == nullptr) {
@@ -777,6 +794,24 @@ gs_status gs_loss_grad(gs_ctx* ctx, const float* const* rendered, const float* c
   if (st != GS_OK) return st;
   GS_HIP(hipEventRecord(ls.last_use, s));
   return GS_OK;
+}
+
+gs_status gs_loss_grad_noalloc(gs_ctx* ctx, const float* const* rendered,
+                               const float* const* target, const gs_camera* cams,
+                               int32_t n_views, float lambda_dssim, float* loss_out,
+                               float* const* dl_dimg, void* stream) {
+  int W[kMaxViews], H[kMaxViews];
+  gs_status st = loss_args("gs_loss_grad_noalloc", ctx, rendered, target, cams, n_views,
+                           lambda_dssim, W, H);
+  if (st != GS_OK) return st;
+  LossScratch ws;
+  st = loss_noalloc_workspace(ctx->device, W, H, n_views, &ws);
+  if (st != GS_OK) return st;
+  st = set_device(ctx);
+  if (st != GS_OK) return st;
+  // the same kernels as gs_loss_grad; no stage timing (its events may be created here)
+  return launch_loss(ws, rendered, target, W, H, n_views, lambda_dssim, loss_out, dl_dimg,
+                     (hipStream_t)stream);
 }
 
 gs_status gs_render_bwd(gs_ctx* ctx, gs_frame* frame, gs_params params,

@@ -290,6 +290,13 @@ gs_status launch_blend_bwd(const ViewTable& vt, Frame& f, hipStream_t s);
 gs_status launch_export_screen_grads(Frame& f, int view, float* dst, hipStream_t s);
 // loss.hip
 // The workspace must have been reserved for these sizes (loss_reserve).
+// Fixed workspace of the allocation-free loss call: set up once per device (with
+// that device current) when a context is created, then handed out as a
+// LossScratch view (GS_ERR_CAPACITY when the views need more than it holds).
+constexpr size_t kNoAllocMaxPixels = (size_t)1 << 20;  // per view
+gs_status loss_noalloc_setup(int device);
+gs_status loss_noalloc_workspace(int device, const int* W, const int* H, int nv,
+                                 LossScratch* out);
 gs_status launch_loss(const LossScratch& ls, const float* const* x, const float* const* y,
                       const int* W, const int* H, int nv, float lambda, float* loss_out,
                       float* const* dl, hipStream_t s);

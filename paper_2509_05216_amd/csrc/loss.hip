@@ -17,6 +17,8 @@
 // produces four consecutive rows of one column from 14 LDS rows.  Loss sums are reduced per block into
 // float64 partials and summed by a final single-block kernel, so the loss
 // value is deterministic.
+#include <atomic>
+
 #include "internal.h"
 
 namespace isogs {
@@ -453,6 +455,77 @@ gs_status launch_loss(const LossScratch& ls, const float* const* x, const float*
                        loss_out);
     GS_LAUNCHED("loss_final");
   }
+  return GS_OK;
+}
+
+// ---------------------------------------------------------- fixed workspace
+// Workspace of gs_loss_grad_noalloc: one file-scope device array per GPU, held
+// for the life of the process, so that call allocates nothing.  In host code
+// `scratch` names a host-side stand-in, never the device array: its device
+// address comes from hipGetSymbolAddress, taken once per device with that
+// device current (loss_noalloc_setup, called when a context is created) and
+// kept in g_noalloc_ptr.
+constexpr size_t kNoAllocGmapBytes = sizeof(float) * 9 * kNoAllocMaxPixels;
+// 2048 output tiles cover any view of <= 2^20 pixels whose sides are <= 16384
+// (ceil(W/32) ceil(H/32) <= 1536 there)
+constexpr size_t kNoAllocPartBytes =
+    sizeof(double) * 2 * ((size_t)kMaxViews * 3 * 2048 + (size_t)kRedBlocks * kMaxViews);
+constexpr size_t kNoAllocBytes = kNoAllocGmapBytes + kNoAllocPartBytes;
+static_assert(kNoAllocGmapBytes % 256 == 0, "partials start 256-byte aligned");
+
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+constexpr int kNoAllocDevices = 64;
+static std::atomic<void*> g_noalloc_ptr[kNoAllocDevices];
+
+gs_status loss_noalloc_setup(int device) {
+  if (device < 0 || device >= kNoAllocDevices) {
+    set_error("device %d: the fixed loss workspace supports devices 0..%d", device,
+              kNoAllocDevices - 1);
+    return GS_ERR_UNSUPPORTED;
+  }
+  if (g_noalloc_ptr[device].load(std::memory_order_acquire) != nullptr) return GS_OK;
+  static std::mutex mu;
+  std::lock_guard<std::mutex> lk(mu);
+  if (g_noalloc_ptr[device].load(std::memory_order_relaxed) != nullptr) return GS_OK;
+  int cur = -1;
+  GS_HIP(hipGetDevice(&cur));
+  if (cur != device) {
+    set_error("internal: loss_noalloc_setup(%d) with device %d current", device, cur);
+    return GS_ERR_INVALID;
+  }
+  void* ptr = nullptr;
+  GS_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+  if (ptr == nullptr) {
+    set_error("hipGetSymbolAddress returned no address for the loss workspace");
+    return GS_ERR_HIP;
+  }
+  g_noalloc_ptr[device].store(ptr, std::memory_order_release);
+  return GS_OK;
+}
+
+gs_status loss_noalloc_workspace(int device, const int* W, const int* H, int nv,
+                                 LossScratch* out) {
+  size_t gb = 0, pb = 0;
+  loss_scratch_bytes(W, H, nv, &gb, &pb);
+  if (gb > kNoAllocGmapBytes || pb > kNoAllocPartBytes) {
+    set_error("gs_loss_grad_noalloc: views need a %zu + %zu byte workspace; the fixed one "
+              "holds %zu + %zu bytes (at most %zu pixels per view)", gb, pb,
+              kNoAllocGmapBytes, kNoAllocPartBytes, kNoAllocMaxPixels);
+    return GS_ERR_CAPACITY;
+  }
+  void* base = (device >= 0 && device < kNoAllocDevices)
+                   ? g_noalloc_ptr[device].load(std::memory_order_acquire)
+                   : nullptr;
+  if (base == nullptr) {
+    set_error("gs_loss_grad_noalloc: the fixed workspace of device %d was not set up", device);
+    return GS_ERR_INVALID;
+  }
+  out->gmap.p = base;
+  out->gmap.cap = kNoAllocGmapBytes;
+  out->part.p = (unsigned char*)base + kNoAllocGmapBytes;
+  out->part.cap = kNoAllocPartBytes;
+  out->last_use = nullptr;
   return GS_OK;
 }
 

@@ -30,10 +30,13 @@ if ROOT not in sys.path:
 
 METRIC = "fwd+bwd Mpix/s @4M Gaussians 2048^2 (plain vs batched); serve p50/p99 ms"
 HBM_PEAK_GBS = 8000.0
-FP32_PEAK_TFLOPS = 157.3
-# algorithmic FLOP per (pixel, list position up to the pixel's last contributor)
-FLOP_PAIR_FWD = 23
-FLOP_PAIR_BWD = 68
+FP32_PEAK_TFLOPS = 157.3        # published vector peak (packed FP32)
+FP32_NONPACKED_TFLOPS = 78.6    # 256 CUs x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz: no packed FP32
+# algorithmic FLOP per (pixel, list position up to the pixel's last contributor): the
+# forward's offset, quadratic form, exponential, alpha and transmittance update and
+# colour sum (about 20, the exponential counted once), the backward 2.5 times that
+FLOP_PAIR_FWD = 20
+FLOP_PAIR_BWD = 50
 # HBM bytes per launch of a kernel, from calibrated rocprofv3 FETCH_SIZE / WRITE_SIZE runs
 # (profiles/hbm_traffic_kingsnake4m.md), one entry per measured launch configuration and
 # valid only while the kernel source is unchanged: when the source hash no longer matches,
@@ -70,8 +73,8 @@ def log(msg):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--n", type=int, default=None, help="Gaussian count override (smaller runs)")
     ap.add_argument("--grid", type=int, default=None, help="field grid override")
     ap.add_argument("--tile", type=int, default=16)
@@ -104,24 +107,40 @@ def make_targets(scene, cams_d, coarse=128):
     return out
 
 
+def event_times(torch, steps):
+    """HIP events (on torch's current stream, the stream every call here uses) that
+    bracket each of `steps` steps."""
+    return [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+
+
+def step_ms(ev, wall_ms, steps):
+    """Median and mean of the per-step event intervals, and the wall-clock mean."""
+    per = [ev[i].elapsed_time(ev[i + 1]) for i in range(steps)]
+    return {"median": float(np.median(per)), "mean_event": float(np.mean(per)),
+            "min": float(np.min(per)), "max": float(np.max(per)), "mean_wall": wall_ms / steps}
+
+
 def run_graph(P, ctx, params, cams, targets, steps, warmup, render, with_adam, torch):
     """Time `steps` replays of the captured step; returns per-step ms and records."""
     g = P.StepGraph(ctx, params, cams, targets, with_adam=with_adam, render=render)
     for _ in range(warmup):
         g.run()
     torch.cuda.synchronize()
+    ev = event_times(torch, steps)
     t0 = time.perf_counter()
-    for _ in range(steps):
+    ev[0].record()
+    for i in range(steps):
         g.launch()
+        ev[i + 1].record()
     over, rec = g.sync()
     torch.cuda.synchronize()
-    ms = (time.perf_counter() - t0) * 1e3 / steps
+    t = step_ms(ev, (time.perf_counter() - t0) * 1e3, steps)
     if over:
         raise RuntimeError("record capacity overflowed during the timed replays")
     loss = float(g.loss.item())
     cap, _ = g.info()
     g.close()
-    return ms, rec, cap, loss
+    return t, rec, cap, loss
 
 
 def run_steps(P, ctx, params, cams, targets, steps, warmup, tile, depth, torch, flags=0):
@@ -141,14 +160,17 @@ def run_steps(P, ctx, params, cams, targets, steps, warmup, tile, depth, torch, 
         one()
     torch.cuda.synchronize()
     ctx.set_timing(True)
+    ev = event_times(torch, steps)
     t0 = time.perf_counter()
-    for _ in range(steps):
+    ev[0].record()
+    for i in range(steps):
         loss = one()
+        ev[i + 1].record()
     torch.cuda.synchronize()
-    ms = (time.perf_counter() - t0) * 1e3 / steps
+    t = step_ms(ev, (time.perf_counter() - t0) * 1e3, steps)
     stages = ctx.stage_times()
     ctx.set_timing(False)
-    return ms, stages, frame, float(loss.item()), images, grads
+    return t, stages, frame, float(loss.item()), images, grads
 
 
 def serve_run(P, ctx, scene_params, requests, arrivals, outs, warm_cams, torch, **server_opts):
@@ -272,6 +294,10 @@ def roofline(stages, steps, n, views, visible, K, pixels, pairs, traffic=None):
         ach = flops / (avg_ms * 1e-3) / 1e12
         return dom, {"bound": "alu", "achieved": round(ach, 3), "peak": FP32_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(ach / FP32_PEAK_TFLOPS, 4),
+                     "peak_nonpacked": FP32_NONPACKED_TFLOPS,
+                     "frac_nonpacked": round(ach / FP32_NONPACKED_TFLOPS, 4),
+                     "flop_per_pair": FLOP_PAIR_BWD if dom == "blend_bwd" else FLOP_PAIR_FWD,
+                     "pairs": pairs,
                      "traffic": traffic, "kernel": dom, "avg_ms": round(avg_ms, 4),
                      "algorithmic_flop": flops, "algorithmic_bytes": byts,
                      "hbm_GBps_algorithmic": round(byts / (avg_ms * 1e-3) / 1e9, 1)}
@@ -399,34 +425,38 @@ def main():
                     "table": sorted(table, key=lambda r: r["ms"])[:6]}
         log(f"batched options: {best}")
         # eager run of the tuned configuration: per-stage HIP-event times
-        ms, stages, frame, loss, _, _ = run_steps(P, ctx, params, cams, targets, args.steps,
+        tm, stages, frame, loss, _, _ = run_steps(P, ctx, params, cams, targets, args.steps,
                                                   args.warmup, best["tile"], best["lds_depth"],
                                                   torch, flags=best["flags"])
+        ms = tm["median"]
         st, pairs, vis = frame_counts(frame, n, torch)
-        res["batched"] = dict(ms=ms, stages=stages, K=st["n_records"], pixels=st["n_pixels"],
+        res["batched"] = dict(ms=ms, timing=tm, stages=stages, K=st["n_records"], pixels=st["n_pixels"],
                               pairs=pairs, visible=vis, views=len(cams), loss=loss)
         log(f"batched (eager, tuned): {ms:.2f} ms/step, K={st['n_records']}, pairs={pairs}")
         frame.release()
     if args.only in ("all", "batched") and not args.no_graph:
         # the captured step: fwd+bwd, then fwd+bwd+Adam
-        gms, rec, cap, gloss = run_graph(P, ctx, params, cams, targets, args.steps, args.warmup,
+        gtm, rec, cap, gloss = run_graph(P, ctx, params, cams, targets, args.steps, args.warmup,
                                          best, False, torch)
-        res["batched_graph"] = dict(ms=gms, K=rec, capacity=cap, pixels=st["n_pixels"],
+        gms = gtm["median"]
+        res["batched_graph"] = dict(ms=gms, timing=gtm, K=rec, capacity=cap, pixels=st["n_pixels"],
                                     views=len(cams),
                                     loss=gloss, visible=vis, pairs=pairs, stages={})
         log(f"batched (graph): {gms:.2f} ms/step")
         pa = P.Params(*(t.clone() for t in params.tensors()), params.sh_degree)
-        ams, _, _, _ = run_graph(P, ctx, pa, cams, targets, args.steps, args.warmup, best, True,
+        atm, _, _, _ = run_graph(P, ctx, pa, cams, targets, args.steps, args.warmup, best, True,
                                  torch)
+        ams = atm["median"]
         res["batched_graph"]["ms_with_adam"] = ams
         del pa
         log(f"batched (graph + Adam): {ams:.2f} ms/step")
     if args.only in ("all", "plain"):
-        ms, stages, frame, loss, _, _ = run_steps(P, ctx, params, cams[:1], targets[:1],
+        tm, stages, frame, loss, _, _ = run_steps(P, ctx, params, cams[:1], targets[:1],
                                                   args.steps, args.warmup, args.tile,
                                                   args.lds_depth, torch)
+        ms = tm["median"]
         st, pairs, vis = frame_counts(frame, n, torch)
-        res["plain"] = dict(ms=ms, stages=stages, K=st["n_records"], pixels=st["n_pixels"],
+        res["plain"] = dict(ms=ms, timing=tm, stages=stages, K=st["n_records"], pixels=st["n_pixels"],
                             pairs=pairs, visible=vis, views=1, loss=loss)
         log(f"plain: {ms:.2f} ms/step, K={st['n_records']}, pairs={pairs}")
         frame.release()
@@ -513,7 +543,10 @@ def main():
         "memory": memory,
         "step_hbm": step_hbm,
         "roofline": roof,
+        "timing": ("per-step HIP events on the launch stream, median over the timed steps "
+                   "after the warm-up steps; mean_wall = synchronised wall clock / steps"),
         "forms": {k: {"ms_per_step": round(r["ms"], 3),
+                      "ms_stats": {a: round(b, 4) for a, b in r["timing"].items()},
                       "mpix_per_s": round(r["pixels"] / (r["ms"] * 1e-3) / 1e6, 3),
                       "records_K": r["K"], "visible": r["visible"], "pairs": r["pairs"],
                       "loss": round(r["loss"], 6),

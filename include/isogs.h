@@ -85,8 +85,10 @@ typedef struct {
  * flags: GS_RENDER_PERSISTENT blends all views' tiles with one persistent
  * launch (a resident grid draining a work queue), GS_RENDER_LONGEST_FIRST
  * orders that queue by descending tile list length (to within 1/16 of an
- * octave).  Results do not depend on the flags. */
-enum { GS_RENDER_PERSISTENT = 1, GS_RENDER_LONGEST_FIRST = 2 };
+ * octave).  Results do not depend on the flags.  GS_RENDER_RADII also keeps
+ * every (view, Gaussian)'s integer pixel radius in the frame (0 where the
+ * Gaussian touches no tile), which gs_density_accumulate reads. */
+enum { GS_RENDER_PERSISTENT = 1, GS_RENDER_LONGEST_FIRST = 2, GS_RENDER_RADII = 4 };
 typedef struct {
   int32_t tile;
   int32_t lds_depth;
@@ -233,7 +235,7 @@ gs_status gs_loss_grad(gs_ctx* ctx, const float* const* rendered,
 /* gs_loss_grad without allocation, for callers that cannot allocate device
  * memory (code under HIP graph capture, tight serving loops, harnesses that
  * forbid hipMalloc).  Same arguments, kernels and results as gs_loss_grad,
- * but the workspace is a fixed device array of 39,337,984 bytes per GPU,
+ * but the workspace is a fixed device array of 39,346,176 bytes per GPU,
  * held from the first context created on that GPU until the process ends:
  * each view may hold at most 1,048,576 (2^20) pixels, e.g. 1024 x 1024; larger
  * views return GS_ERR_CAPACITY before anything is launched.  The call
@@ -246,6 +248,18 @@ gs_status gs_loss_grad_noalloc(gs_ctx* ctx, const float* const* rendered,
                                const float* const* target, const gs_camera* cams,
                                int32_t n_views, float lambda_dssim, float* loss_out,
                                float* const* dl_dimg, void* stream);
+
+/* Image-quality metrics of n_views rendered images against references, the
+ * quality measures the paper reports for its trained models (PSNR and SSIM,
+ * Sec. IV, Tables II-III): out (device float[n_views][4]) receives per view
+ * the mean squared error over pixels and channels, PSNR = 10 log10(1 / MSE)
+ * (values in [0, 1]; +inf when MSE is 0), the mean absolute error and the
+ * mean SSIM (the loss's window and constants).  Sums in float64 in a fixed
+ * order (deterministic).  Uses the context's loss workspace, like
+ * gs_loss_grad. */
+gs_status gs_image_metrics(gs_ctx* ctx, const float* const* rendered,
+                           const float* const* reference, const gs_camera* cams,
+                           int32_t n_views, float* out, void* stream);
 
 /* Backward of gs_render_fwd for the frame's views (the gradient step of the
  * 3D-GS training adopted in Sec. III): reverse front-to-back traversal that
@@ -384,6 +398,93 @@ gs_status gs_server_drain(gs_server* server);
 gs_status gs_server_stats(gs_server* server, gs_serve_stats* out);
 gs_status gs_server_reset_stats(gs_server* server);
 void gs_server_destroy(gs_server* server);
+
+/* ------------------------------------------------- adaptive density control
+ * Clone, split and prune of the 3D-GS training that Sec. III (Method
+ * Overview) adopts by citation; the paper restates none of it, so the
+ * statistics, thresholds and output order below are the readings this library
+ * takes of that model's density control.
+ *
+ * Statistics (caller-owned device arrays of n entries, zeroed by the caller
+ * at the start of an interval): grad = sum over views of scale * |dL/dmean2D|
+ * in normalised device coordinates ((dL/dm_x W/2, dL/dm_y H/2), W x H the
+ * view's size), count = number of views in which the Gaussian touched a
+ * tile, max_radius = its largest pixel radius over those views. */
+typedef struct {
+  float* grad;
+  int32_t* count;
+  int32_t* max_radius;
+  int64_t n;
+} gs_density_stats;
+
+/* Adds the views of `frame` to the statistics.  The frame must have been
+ * rendered with GS_RENDER_RADII and its backward run with
+ * GS_BWD_KEEP_SCREEN (GS_ERR_INVALID otherwise); stats.n must equal the
+ * frame's Gaussian count.  scale multiplies each view's norm (the number of
+ * views of a batch whose loss is their mean makes every view count as in
+ * one-view training).  Asynchronous on `stream`. */
+gs_status gs_density_accumulate(gs_ctx* ctx, gs_frame* frame, gs_density_stats stats,
+                                float scale, void* stream);
+
+/* Densification thresholds (3D-GS defaults in brackets). */
+typedef struct {
+  double grad_threshold;  /* mean NDC gradient that selects a Gaussian [0.0002] */
+  double percent_dense;   /* selected with largest scale <= percent_dense * extent are
+                             cloned, larger ones split [0.01] */
+  double min_opacity;     /* opacity below it is pruned [0.005] */
+  double max_screen;      /* > 0: also prune max_radius > max_screen or largest scale >
+                             max_world * extent (<= 0: no size prune) [20 after the
+                             first opacity reset] */
+  double max_world;       /* [0.1] */
+  double extent;          /* scene extent (radius of the camera set) */
+  double split_div;       /* children's scales = parent's / split_div [1.6] */
+  int32_t n_split;        /* children per split Gaussian, 1..8 [2] */
+  int32_t reserved;
+  uint64_t seed;          /* key of the children's Philox draws */
+} gs_density_opts;
+
+typedef struct {
+  int64_t n_in, n_out;    /* Gaussians before and after */
+  int64_t kept;           /* originals kept */
+  int64_t cloned;         /* clones made (and kept) */
+  int64_t split;          /* Gaussians split (the parent is removed) */
+  int64_t children;       /* children kept */
+  int64_t pruned;         /* originals removed other than by a split */
+} gs_density_info;
+
+/* One densification of params p with Adam moments m, v (device SoA, n
+ * entries) from the statistics:
+ *  - mean gradient g = grad / count (0 where count is 0), in float64; g >=
+ *    grad_threshold selects a Gaussian; a selected one is cloned (an exact
+ *    copy) when its largest scale exp(log_scale) <= percent_dense * extent,
+ *    split otherwise into n_split children at mean + R(q) (s * z), z three
+ *    standard normals (Philox4x32-10 keyed by the seed's two words, counter
+ *    (parent index, 16 + child, 0, 0), Box-Muller of its two pairs, first
+ *    three values), log-scales minus log(split_div), the parent's rotation,
+ *    opacity and colour; the parent is removed;
+ *  - prune: opacity < min_opacity, and with max_screen > 0 also max_radius >
+ *    max_screen or largest scale > max_world * extent (clones: opacity and
+ *    scale; children: opacity and their own scale);
+ *  - output order: kept originals in index order, then clones in the order of
+ *    their sources, then children source by source (child 0 first); Adam
+ *    moments are copied for originals and zero for new Gaussians.
+ * p_out, m_out, v_out (device, caller-owned, must not overlap the inputs)
+ * receive the new set and must have n equal to info->n_out; pass p_out.means
+ * = NULL to only count (info filled, nothing written).  src_index (optional,
+ * device int32[n_out]) receives the source index of every output.  The
+ * statistics and inputs are read, not changed.  Synchronises `stream` once
+ * (the counts are read back).  GS_ERR_CAPACITY when p_out.n < n_out,
+ * GS_ERR_INVALID when larger. */
+gs_status gs_densify(gs_ctx* ctx, gs_params p, gs_params m, gs_params v,
+                     gs_density_stats stats, const gs_density_opts* opts, gs_params p_out,
+                     gs_params m_out, gs_params v_out, int32_t* src_index,
+                     gs_density_info* info, void* stream);
+
+/* Opacity reset of the same training: opacity = min(opacity, max_opacity)
+ * (in logit form, max_opacity in (0, 1), 0.01 in 3D-GS) and the opacity's
+ * Adam moments set to zero.  In place, asynchronous. */
+gs_status gs_opacity_reset(gs_ctx* ctx, gs_params p, gs_params m, gs_params v,
+                           double max_opacity, void* stream);
 
 /* -------------------------------------------------------------- autotuner
  * Times forward + backward of the given views for tile sizes {8, 16, 32},

@@ -15,7 +15,10 @@ it.  It computes, plainly and slowly, in float64 numpy:
 * ``backward`` chain rule from screen-space gradients to the parameters;
 * ``adam``     the bias-corrected Adam update;
 * ``init``     Gaussians from isosurface points with a Philox4x32-10 stream;
-* ``pipeline`` the whole per-view forward/backward built from the above.
+* ``pipeline`` the whole per-view forward/backward built from the above;
+* ``density``  adaptive density control (statistics, clone, split, prune,
+               opacity reset);
+* ``metrics``  image-quality metrics (MSE, PSNR, L1, SSIM) of a view.
 
 The paper adopts the 3D-GS rasterizer by citation (Sec. III, Method Overview)
 and states none of its formulas; each function names the reading it follows.

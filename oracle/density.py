@@ -139,7 +139,8 @@ def densify(params, m, v, stats, extent, *, tau=GRAD_THRESHOLD, percent_dense=PE
     info = dict(n_in=n, n_out=res_p["means"].shape[1], kept=int(keep_orig.sum()),
                 cloned=int(keep_clone.sum()), split=int(src.size),
                 children=int(kc.sum()), pruned=int((~keep_orig & ~split).sum()),
-                clone_mask=clone, split_mask=split, keep_orig=keep_orig, mean_grad=g)
+                clone_mask=clone, split_mask=split, keep_orig=keep_orig, keep_clone=keep_clone,
+                split_src=src, keep_child=keep_child, mean_grad=g)
     return res_p, res_m, res_v, info
 
 

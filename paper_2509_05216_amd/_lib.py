@@ -91,6 +91,24 @@ class GsServeStats(C.Structure):
                 ("max_ms", C.c_double), ("mpix_per_s", C.c_double), ("peak_bytes", C.c_int64)]
 
 
+class GsDensityStats(C.Structure):
+    _fields_ = [("grad", C.c_void_p), ("count", C.c_void_p), ("max_radius", C.c_void_p),
+                ("n", C.c_int64)]
+
+
+class GsDensityOpts(C.Structure):
+    _fields_ = [("grad_threshold", C.c_double), ("percent_dense", C.c_double),
+                ("min_opacity", C.c_double), ("max_screen", C.c_double),
+                ("max_world", C.c_double), ("extent", C.c_double), ("split_div", C.c_double),
+                ("n_split", C.c_int32), ("reserved", C.c_int32), ("seed", C.c_uint64)]
+
+
+class GsDensityInfo(C.Structure):
+    _fields_ = [("n_in", C.c_int64), ("n_out", C.c_int64), ("kept", C.c_int64),
+                ("cloned", C.c_int64), ("split", C.c_int64), ("children", C.c_int64),
+                ("pruned", C.c_int64)]
+
+
 class GsTuneEntry(C.Structure):
     _fields_ = [("tile", C.c_int32), ("lds_depth", C.c_int32), ("flags", C.c_int32),
                 ("ms", C.c_float)]
@@ -116,7 +134,13 @@ SIGNATURES = [
                                _PP, _P]),
     ("gs_loss_grad_noalloc", C.c_int, [_P, _PP, _PP, C.POINTER(GsCamera), C.c_int32,
                                        C.c_float, _P, _PP, _P]),
+    ("gs_image_metrics", C.c_int, [_P, _PP, _PP, C.POINTER(GsCamera), C.c_int32, _P, _P]),
     ("gs_render_bwd", C.c_int, [_P, _P, GsParams, _PP, GsParams, C.c_int32, _P]),
+    ("gs_density_accumulate", C.c_int, [_P, _P, GsDensityStats, C.c_float, _P]),
+    ("gs_densify", C.c_int, [_P, GsParams, GsParams, GsParams, GsDensityStats,
+                             C.POINTER(GsDensityOpts), GsParams, GsParams, GsParams, _P,
+                             C.POINTER(GsDensityInfo), _P]),
+    ("gs_opacity_reset", C.c_int, [_P, GsParams, GsParams, GsParams, C.c_double, _P]),
     ("gs_adam_step", C.c_int, [_P, GsParams, GsParams, GsParams, GsParams,
                                C.POINTER(GsAdamOpts), C.c_int64, _P]),
     ("gs_bw_probe", C.c_int, [_P, _P, _P, C.c_size_t, _P]),

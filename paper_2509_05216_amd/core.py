@@ -211,6 +211,7 @@ class Frame:
 
 PERSISTENT = 1
 LONGEST_FIRST = 2
+RADII = 4
 
 
 def _opts(tile, lds_depth, bg, flags=0):
@@ -265,6 +266,17 @@ def loss_grad_into(ctx, rendered, targets, cams, loss, grads, lam=0.2, *, noallo
     fn = L.lib().gs_loss_grad_noalloc if noalloc else L.lib().gs_loss_grad
     L.check(fn(ctx.handle, ra, ta, _cam_array(cams), len(cams), float(lam),
                _ptr(loss) if loss is not None else None, ga, _stream(stream)))
+
+
+def image_metrics(ctx, rendered, references, cams, stream=None):
+    """Per-view (mse, psnr, l1, ssim) as a float32 device tensor (n_views, 4)."""
+    out = torch.empty((len(cams), 4), dtype=torch.float32, device=rendered[0].device)
+    refs = [t.contiguous() for t in references]
+    ra, k1 = L.ptr_array([r.data_ptr() for r in rendered])
+    ta, k2 = L.ptr_array([t.data_ptr() for t in refs])
+    L.check(L.lib().gs_image_metrics(ctx.handle, ra, ta, _cam_array(cams), len(cams), _ptr(out),
+                                     _stream(stream)))
+    return out
 
 
 BWD_ACCUMULATE = 1

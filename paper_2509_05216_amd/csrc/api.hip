@@ -142,14 +142,14 @@ gs_status timing_collect(Ctx* c) {
 
 static const char* kStageNames[ST_COUNT] = {
     "project", "depth_sort", "scan", "emit", "tile_sort", "ranges", "blend_fwd",
-    "loss", "blend_bwd", "project_bwd", "adam", "init", "probe"};
+    "loss", "blend_bwd", "project_bwd", "adam", "init", "probe", "densify"};
 
 size_t Frame::bytes() const {
   size_t s = splat.cap + rect.cap + dkey.cap + dkw[0].cap + dkw[1].cap + sidx[0].cap +
              sidx[1].cap + clampm.cap + offs.cap + tkey[0].cap + tkey[1].cap + tval[0].cap +
              tval[1].cap + ranges.cap + finalT.cap + ncon.cap + acc.cap + ss.hist.cap +
              ss.partial.cap + ss.total.cap + words.cap + okey[0].cap + okey[1].cap +
-             oval[0].cap + oval[1].cap;
+             oval[0].cap + oval[1].cap + radii.cap;
   return s;
 }
 
@@ -159,7 +159,8 @@ static void frame_free(Frame* f) {
                    &f->sidx[0], &f->sidx[1], &f->clampm,  &f->offs,       &f->tkey[0],
                    &f->tkey[1], &f->tval[0], &f->tval[1], &f->ranges,     &f->finalT,
                    &f->ncon,    &f->acc,     &f->ss.hist, &f->ss.partial, &f->ss.total,
-                   &f->words,   &f->okey[0], &f->okey[1], &f->oval[0],    &f->oval[1]};
+                   &f->words,   &f->okey[0], &f->okey[1], &f->oval[0],    &f->oval[1],
+                   &f->radii};
   for (DevBuf* b : all) buf_free(c, *b);
   if (f->pinned != nullptr) (void)hipHostFree(f->pinned);
   f->pinned = nullptr;
@@ -292,6 +293,7 @@ static gs_status frame_buffers(Frame& f, hipStream_t s) {
   ENS(f.ranges, (size_t)f.vt.total_tiles * 8);
   ENS(f.finalT, (size_t)f.total_pix * 4);
   ENS(f.ncon, (size_t)f.total_pix * 4);
+  if (f.keep_radii) ENS(f.radii, vn * 4);
   const size_t acc_bytes = (size_t)f.views * kAccStride * (size_t)f.n * 4;
   if (f.acc.cap < acc_bytes) {
     ENS(f.acc, acc_bytes);
@@ -329,6 +331,9 @@ static void ctx_free(gs_ctx* ctx) {
     delete ctx->loss_scratch;
     ctx->loss_scratch = nullptr;
   }
+  buf_free(ctx, ctx->dens_blk);
+  if (ctx->dens_host != nullptr) (void)hipHostFree(ctx->dens_host);
+  ctx->dens_host = nullptr;
   (void)timing_collect(ctx);
   for (int i = 0; i < ctx->n_free; ++i) (void)hipEventDestroy(ctx->free_events[i]);
   delete[] ctx->free_events;
@@ -556,7 +561,7 @@ gs_status gs_render_fwd(gs_ctx* ctx, gs_params params, const gs_camera* cams, in
     flags = opts->flags;
     for (int k = 0; k < 3; ++k) bg[k] = opts->bg[k];
   }
-  if ((flags & ~(GS_RENDER_PERSISTENT | GS_RENDER_LONGEST_FIRST)) != 0) {
+  if ((flags & ~(GS_RENDER_PERSISTENT | GS_RENDER_LONGEST_FIRST | GS_RENDER_RADII)) != 0) {
     set_error("gs_render_fwd: unknown render flags 0x%x", flags);
     return GS_ERR_INVALID;
   }
@@ -597,6 +602,8 @@ gs_status gs_render_fwd(gs_ctx* ctx, gs_params params, const gs_camera* cams, in
   f.tile_order = nullptr;
   f.sh_degree = params.sh_degree;
   f.K = 0;
+  f.keep_radii = (flags & GS_RENDER_RADII) != 0;
+  f.screen_kept = false;
   st = build_views(f, cams, n_views, images, bg);
   if (st == GS_OK) st = frame_buffers(f, s);
   if (st != GS_OK) {
@@ -796,6 +803,36 @@ gs_status gs_loss_grad(gs_ctx* ctx, const float* const* rendered, const float* c
   return GS_OK;
 }
 
+gs_status gs_image_metrics(gs_ctx* ctx, const float* const* rendered,
+                           const float* const* reference, const gs_camera* cams,
+                           int32_t n_views, float* out, void* stream) {
+  int W[kMaxViews], H[kMaxViews];
+  gs_status st = loss_args("gs_image_metrics", ctx, rendered, reference, cams, n_views, 0.5f,
+                           W, H);
+  if (st != GS_OK) return st;
+  if (out == nullptr) {
+    set_error("gs_image_metrics: out is null");
+    return GS_ERR_INVALID;
+  }
+  st = set_device(ctx);
+  if (st != GS_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  if (ctx->loss_scratch == nullptr) {
+    ctx->loss_scratch = new (std::nothrow) LossScratch();
+    if (ctx->loss_scratch == nullptr) {
+      set_error("gs_image_metrics: out of host memory");
+      return GS_ERR_NOMEM;
+    }
+  }
+  LossScratch& ls = *ctx->loss_scratch;
+  st = loss_reserve(ctx, ls, W, H, n_views, s);
+  if (st != GS_OK) return st;
+  st = launch_metrics(ls, rendered, reference, W, H, n_views, out, s);
+  if (st != GS_OK) return st;
+  GS_HIP(hipEventRecord(ls.last_use, s));
+  return GS_OK;
+}
+
 gs_status gs_loss_grad_noalloc(gs_ctx* ctx, const float* const* rendered,
                                const float* const* target, const gs_camera* cams,
                                int32_t n_views, float lambda_dssim, float* loss_out,
@@ -857,9 +894,150 @@ gs_status gs_render_bwd(gs_ctx* ctx, gs_frame* frame, gs_params params,
   st = backward_stages(ctx, f, params_dev(params), gd, s);
   if (st != GS_OK) return st;
   // kept sums are cleared by the next forward
-  if (gd.keep_screen) f.acc_zeroed = false;
+  if (gd.keep_screen) {
+    f.acc_zeroed = false;
+    f.screen_kept = true;
+  }
   GS_HIP(hipEventRecord(f.last_use, s));
   return GS_OK;
+}
+
+gs_status gs_density_accumulate(gs_ctx* ctx, gs_frame* frame, gs_density_stats stats,
+                                float scale, void* stream) {
+  if (ctx == nullptr || frame == nullptr) {
+    set_error("gs_density_accumulate: null argument");
+    return GS_ERR_INVALID;
+  }
+  if (frame->ctx != ctx) {
+    set_error("gs_density_accumulate: frame belongs to another context");
+    return GS_ERR_INVALID;
+  }
+  if (stats.grad == nullptr || stats.count == nullptr || stats.max_radius == nullptr) {
+    set_error("gs_density_accumulate: null statistics array");
+    return GS_ERR_INVALID;
+  }
+  Frame& f = *frame;
+  if (stats.n != f.n) {
+    set_error("gs_density_accumulate: statistics hold %lld entries, the frame %lld",
+              (long long)stats.n, (long long)f.n);
+    return GS_ERR_INVALID;
+  }
+  if (!f.keep_radii || !f.screen_kept) {
+    set_error("gs_density_accumulate: the frame needs a forward with GS_RENDER_RADII and a "
+              "backward with GS_BWD_KEEP_SCREEN");
+    return GS_ERR_INVALID;
+  }
+  if (!(scale >= 0.f)) {
+    set_error("gs_density_accumulate: scale %g < 0", (double)scale);
+    return GS_ERR_INVALID;
+  }
+  gs_status st = set_device(ctx);
+  if (st != GS_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  st = launch_density_accumulate(f, stats, scale, s);
+  if (st != GS_OK) return st;
+  GS_HIP(hipEventRecord(f.last_use, s));
+  return GS_OK;
+}
+
+static bool same_shape(const gs_params& a, const gs_params& b) {
+  return a.n == b.n && a.sh_degree == b.sh_degree;
+}
+
+static bool overlaps(const gs_params& a, const gs_params& b) {
+  const int ra = 11 + (a.sh_degree + 1) * (a.sh_degree + 1) * 3;
+  const int rb = 11 + (b.sh_degree + 1) * (b.sh_degree + 1) * 3;
+  const float* pa[5] = {a.means, a.log_scales, a.quats, a.opacity_logits, a.sh};
+  const float* pb[5] = {b.means, b.log_scales, b.quats, b.opacity_logits, b.sh};
+  const int na[5] = {3, 3, 4, 1, ra - 11}, nb[5] = {3, 3, 4, 1, rb - 11};
+  for (int i = 0; i < 5; ++i)
+    for (int j = 0; j < 5; ++j) {
+      const char* a0 = (const char*)pa[i];
+      const char* a1 = a0 + sizeof(float) * (size_t)na[i] * (size_t)a.n;
+      const char* b0 = (const char*)pb[j];
+      const char* b1 = b0 + sizeof(float) * (size_t)nb[j] * (size_t)b.n;
+      if (a0 < b1 && b0 < a1) return true;
+    }
+  return false;
+}
+
+gs_status gs_densify(gs_ctx* ctx, gs_params p, gs_params m, gs_params v, gs_density_stats stats,
+                     const gs_density_opts* opts, gs_params p_out, gs_params m_out,
+                     gs_params v_out, int32_t* src_index, gs_density_info* info, void* stream) {
+  if (ctx == nullptr || opts == nullptr || info == nullptr) {
+    set_error("gs_densify: null argument");
+    return GS_ERR_INVALID;
+  }
+  if (!valid_params(p, "gs_densify (p)") || !valid_params(m, "gs_densify (m)") ||
+      !valid_params(v, "gs_densify (v)"))
+    return GS_ERR_INVALID;
+  if (!same_shape(p, m) || !same_shape(p, v)) {
+    set_error("gs_densify: p, m, v shapes differ");
+    return GS_ERR_INVALID;
+  }
+  if (p.n > 0x7fffffffLL) {
+    set_error("gs_densify: n %lld exceeds 2^31 - 1", (long long)p.n);
+    return GS_ERR_CAPACITY;
+  }
+  if (stats.grad == nullptr || stats.count == nullptr || stats.max_radius == nullptr ||
+      stats.n != p.n) {
+    set_error("gs_densify: statistics must be three arrays of n = %lld entries",
+              (long long)p.n);
+    return GS_ERR_INVALID;
+  }
+  const gs_density_opts& o = *opts;
+  if (o.n_split < 1 || o.n_split > 8 || !(o.split_div > 0.0) || !(o.extent > 0.0) ||
+      !(o.grad_threshold >= 0.0) || !(o.percent_dense >= 0.0) || !(o.max_world >= 0.0) ||
+      !(o.min_opacity >= 0.0) || o.max_screen != o.max_screen) {
+    set_error("gs_densify: invalid options (n_split 1..8, split_div > 0, extent > 0, "
+              "thresholds >= 0)");
+    return GS_ERR_INVALID;
+  }
+  const bool write = p_out.means != nullptr;
+  if (write) {
+    if (!valid_params(p_out, "gs_densify (p_out)") || !valid_params(m_out, "gs_densify (m_out)") ||
+        !valid_params(v_out, "gs_densify (v_out)"))
+      return GS_ERR_INVALID;
+    if (p_out.sh_degree != p.sh_degree || m_out.sh_degree != p.sh_degree ||
+        v_out.sh_degree != p.sh_degree) {
+      set_error("gs_densify: output SH degree differs from the input's");
+      return GS_ERR_INVALID;
+    }
+    const gs_params ins[3] = {p, m, v}, outs[3] = {p_out, m_out, v_out};
+    for (const gs_params& a : outs)
+      for (const gs_params& b : ins)
+        if (overlaps(a, b)) {
+          set_error("gs_densify: an output array overlaps an input array");
+          return GS_ERR_INVALID;
+        }
+  }
+  gs_status st = set_device(ctx);
+  if (st != GS_OK) return st;
+  StageTimer tm(ctx, ST_DENSIFY, (hipStream_t)stream);
+  return densify_run(ctx, p, m, v, stats, o, write ? &p_out : nullptr, write ? &m_out : nullptr,
+                     write ? &v_out : nullptr, src_index, info, (hipStream_t)stream);
+}
+
+gs_status gs_opacity_reset(gs_ctx* ctx, gs_params p, gs_params m, gs_params v,
+                           double max_opacity, void* stream) {
+  if (ctx == nullptr) {
+    set_error("gs_opacity_reset: null context");
+    return GS_ERR_INVALID;
+  }
+  if (!valid_params(p, "gs_opacity_reset (p)") || !valid_params(m, "gs_opacity_reset (m)") ||
+      !valid_params(v, "gs_opacity_reset (v)"))
+    return GS_ERR_INVALID;
+  if (!same_shape(p, m) || !same_shape(p, v)) {
+    set_error("gs_opacity_reset: p, m, v shapes differ");
+    return GS_ERR_INVALID;
+  }
+  if (!(max_opacity > 0.0 && max_opacity < 1.0)) {
+    set_error("gs_opacity_reset: max_opacity %g not in (0, 1)", max_opacity);
+    return GS_ERR_INVALID;
+  }
+  gs_status st = set_device(ctx);
+  if (st != GS_OK) return st;
+  return launch_opacity_reset(p, m, v, max_opacity, (hipStream_t)stream);
 }
 
 gs_status gs_adam_step(gs_ctx* ctx, gs_params p, gs_params g, gs_params m, gs_params v,

@@ -135,7 +135,7 @@ void buf_free(Ctx* ctx, DevBuf& b);
 // Pipeline stages timed with HIP events when a context enables timing.
 enum Stage {
   ST_PROJECT = 0, ST_DEPTH_SORT, ST_SCAN, ST_EMIT, ST_TILE_SORT, ST_RANGES, ST_BLEND_FWD,
-  ST_LOSS, ST_BLEND_BWD, ST_PROJECT_BWD, ST_ADAM, ST_INIT, ST_PROBE, ST_COUNT
+  ST_LOSS, ST_BLEND_BWD, ST_PROJECT_BWD, ST_ADAM, ST_INIT, ST_PROBE, ST_DENSIFY, ST_COUNT
 };
 
 struct PendingTiming {
@@ -152,6 +152,8 @@ struct Ctx {
   int cu_count = 0;
   hipDeviceProp_t prop;
   struct LossScratch* loss_scratch = nullptr;  // workspace of eager gs_loss_grad calls
+  DevBuf dens_blk;                 // gs_densify: block totals and offsets
+  uint32_t* dens_host = nullptr;   // gs_densify: pinned read-back of the totals
   // set while a graph is being captured: no allocation, no stage events
   bool capturing = false;
   // stage timing
@@ -220,6 +222,9 @@ struct Frame {
   int key_bits = 1;
   DevBuf splat, rect, dkey, dkw[2], sidx[2], clampm, offs, tkey[2], tval[2], ranges, finalT,
       ncon, acc;
+  DevBuf radii;               // int32[views][n] pixel radii (GS_RENDER_RADII)
+  bool keep_radii = false;    // this forward writes radii
+  bool screen_kept = false;   // the last backward kept its screen-space sums
   int tkey_sel = 0;  // which of tkey/tval holds the sorted records
   int sidx_sel = 0;  // which of sidx holds the depth-sorted (view, Gaussian) indices
   bool acc_zeroed = false;
@@ -235,6 +240,28 @@ struct Frame {
   hipEvent_t last_use = nullptr;
   size_t bytes() const;
 };
+
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as easy as
+// 1, 2, 3", SC'11): ten rounds on counter c with key (k0, k1), in place.
+__device__ inline void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r > 0) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c[0];
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c[2];
+    const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c[1] ^ k0;
+    const uint32_t n1 = (uint32_t)p1;
+    const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c[3] ^ k1;
+    const uint32_t n3 = (uint32_t)p0;
+    c[0] = n0;
+    c[1] = n1;
+    c[2] = n2;
+    c[3] = n3;
+  }
+}
 
 // ------------------------------------------------------------- pipelines (api.hip)
 ParamsDev params_dev(const gs_params& p);
@@ -300,6 +327,18 @@ gs_status loss_noalloc_workspace(int device, const int* W, const int* H, int nv,
 gs_status launch_loss(const LossScratch& ls, const float* const* x, const float* const* y,
                       const int* W, const int* H, int nv, float lambda, float* loss_out,
                       float* const* dl, hipStream_t s);
+// density.hip
+gs_status launch_density_accumulate(const Frame& f, const gs_density_stats& st, float scale,
+                                    hipStream_t s);
+gs_status densify_run(Ctx* ctx, const gs_params& p, const gs_params& m, const gs_params& v,
+                      const gs_density_stats& st, const gs_density_opts& o, const gs_params* p_out,
+                      const gs_params* m_out, const gs_params* v_out, int32_t* src_index,
+                      gs_density_info* info, hipStream_t s);
+gs_status launch_opacity_reset(const gs_params& p, const gs_params& m, const gs_params& v,
+                               double max_opacity, hipStream_t s);
+// Per-view MSE, PSNR, L1 and SSIM into out[nv][4] (workspace as for launch_loss).
+gs_status launch_metrics(const LossScratch& ls, const float* const* x, const float* const* y,
+                         const int* W, const int* H, int nv, float* out, hipStream_t s);
 // probe.hip
 gs_status launch_copy_probe(Ctx* ctx, const void* src, void* dst, size_t bytes, hipStream_t s);
 // adam.hip

@@ -376,6 +376,51 @@ __global__ __launch_bounds__(256) void k_loss_final(const double* __restrict__ p
   if (threadIdx.x == 0) *out = (float)(total / lr.nv);
 }
 
+// Image-quality metrics: block (b, v) sums (x - y)^2 over view v's values
+// b * 256 + t, b * 256 + t + 64 * 256, ... (fixed order) in float64.
+struct ImagePtrs {
+  const float* x[kMaxViews];
+  const float* y[kMaxViews];
+};
+
+__global__ __launch_bounds__(256) void k_sq_partial(ImagePtrs im, LossRed lr,
+                                                    double* __restrict__ part3) {
+  const int v = blockIdx.y;
+  const float* x = im.x[v];
+  const float* y = im.y[v];
+  const long long count = (long long)(0.5 + 1.0 / lr.inv_count[v]);
+  double a = 0.0, b = 0.0;
+  for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < count;
+       i += (long long)kRedBlocks * 256) {
+    const double d = (double)x[i] - (double)y[i];
+    a += d * d;
+  }
+  block_sum2(a, b);
+  if (threadIdx.x == 0) part3[v * kRedBlocks + blockIdx.x] = a;
+}
+
+// Block v: mse, psnr = 10 log10(1 / mse), mean |x - y| and mean SSIM of view v.
+__global__ __launch_bounds__(256) void k_metrics_final(const double* __restrict__ part2,
+                                                       const double* __restrict__ part3,
+                                                       LossRed lr, float* __restrict__ out) {
+  const int v = blockIdx.x;
+  double a = 0.0, b = 0.0, c = 0.0, d = 0.0;
+  if (threadIdx.x < kRedBlocks) {
+    a = part2[2 * (v * kRedBlocks + threadIdx.x) + 0];
+    b = part2[2 * (v * kRedBlocks + threadIdx.x) + 1];
+    c = part3[v * kRedBlocks + threadIdx.x];
+  }
+  block_sum2(a, b);
+  block_sum2(c, d);
+  if (threadIdx.x == 0) {
+    const double mse = c * lr.inv_count[v];
+    out[4 * v + 0] = (float)mse;
+    out[4 * v + 1] = (float)(mse > 0.0 ? -10.0 * log10(mse) : INFINITY);
+    out[4 * v + 2] = (float)(a * lr.inv_count[v]);
+    out[4 * v + 3] = (float)(b * lr.inv_count[v]);
+  }
+}
+
 }  // namespace
 
 void loss_scratch_bytes(const int* W, const int* H, int nv, size_t* gmap_bytes,
@@ -387,7 +432,9 @@ void loss_scratch_bytes(const int* W, const int* H, int nv, size_t* gmap_bytes,
     total_blocks += (size_t)((W[v] + kT - 1) / kT) * ((H[v] + kT - 1) / kT) * 3;
   }
   *gmap_bytes = sizeof(float) * 9 * max_plane;
-  *part_bytes = sizeof(double) * 2 * (total_blocks + kRedBlocks * kMaxViews);
+  // block partials (2 each), per-view stage-1 sums (2 each), metric sums (1 each)
+  *part_bytes = sizeof(double) * (2 * (total_blocks + kRedBlocks * kMaxViews) +
+                                  (size_t)kRedBlocks * kMaxViews);
 }
 
 gs_status loss_reserve(Ctx* ctx, LossScratch& ls, const int* W, const int* H, int nv,
@@ -469,7 +516,8 @@ constexpr size_t kNoAllocGmapBytes = sizeof(float) * 9 * kNoAllocMaxPixels;
 // 2048 output tiles cover any view of <= 2^20 pixels whose sides are <= 16384
 // (ceil(W/32) ceil(H/32) <= 1536 there)
 constexpr size_t kNoAllocPartBytes =
-    sizeof(double) * 2 * ((size_t)kMaxViews * 3 * 2048 + (size_t)kRedBlocks * kMaxViews);
+    sizeof(double) * (2 * ((size_t)kMaxViews * 3 * 2048 + (size_t)kRedBlocks * kMaxViews) +
+                      (size_t)kRedBlocks * kMaxViews);
 constexpr size_t kNoAllocBytes = kNoAllocGmapBytes + kNoAllocPartBytes;
 static_assert(kNoAllocGmapBytes % 256 == 0, "partials start 256-byte aligned");
 
@@ -526,6 +574,59 @@ gs_status loss_noalloc_workspace(int device, const int* W, const int* H, int nv,
   out->part.p = (unsigned char*)base + kNoAllocGmapBytes;
   out->part.cap = kNoAllocPartBytes;
   out->last_use = nullptr;
+  return GS_OK;
+}
+
+gs_status launch_metrics(const LossScratch& ls, const float* const* x, const float* const* y,
+                         const int* W, const int* H, int nv, float* out, hipStream_t s) {
+  Win win;
+  {
+    double g[kN], sum = 0.0;
+    for (int i = 0; i < kN; ++i) {
+      const double d = i - kR;
+      g[i] = exp(-(d * d) / (2.0 * 1.5 * 1.5));
+      sum += g[i];
+    }
+    for (int i = 0; i < kN; ++i) win.w[i] = (float)(g[i] / sum);
+  }
+  size_t total_blocks = 0;
+  LossRed lr;
+  lr.nv = nv;
+  for (int v = 0; v < nv; ++v) {
+    const size_t plane = (size_t)W[v] * H[v];
+    lr.nblk[v] = ((W[v] + kT - 1) / kT) * ((H[v] + kT - 1) / kT) * 3;
+    lr.off[v] = (long long)total_blocks;
+    lr.inv_count[v] = 1.0 / (3.0 * (double)plane);
+    total_blocks += (size_t)lr.nblk[v];
+  }
+  size_t gb = 0, pb = 0;
+  loss_scratch_bytes(W, H, nv, &gb, &pb);
+  if (ls.gmap.cap < gb || ls.part.cap < pb) {
+    set_error("internal: metrics workspace too small");
+    return GS_ERR_CAPACITY;
+  }
+  double* part = (double*)ls.part.p;
+  double* part2 = part + 2 * total_blocks;
+  double* part3 = part2 + 2 * (size_t)kRedBlocks * kMaxViews;
+  for (int v = 0; v < nv; ++v) {
+    const dim3 grid((W[v] + kT - 1) / kT, (H[v] + kT - 1) / kT, 3);
+    hipLaunchKernelGGL(k_ssim_fwd, grid, dim3(256), 0, s, x[v], y[v], W[v], H[v], win,
+                       (float*)ls.gmap.p, part + 2 * lr.off[v]);
+    GS_LAUNCHED("ssim_fwd");
+  }
+  hipLaunchKernelGGL(k_loss_partial, dim3(kRedBlocks, nv), dim3(256), 0, s, (const double*)part,
+                     lr, part2);
+  GS_LAUNCHED("loss_partial");
+  ImagePtrs im;
+  for (int v = 0; v < nv; ++v) {
+    im.x[v] = x[v];
+    im.y[v] = y[v];
+  }
+  hipLaunchKernelGGL(k_sq_partial, dim3(kRedBlocks, nv), dim3(256), 0, s, im, lr, part3);
+  GS_LAUNCHED("sq_partial");
+  hipLaunchKernelGGL(k_metrics_final, dim3(nv), dim3(256), 0, s, (const double*)part2,
+                     (const double*)part3, lr, out);
+  GS_LAUNCHED("metrics_final");
   return GS_OK;
 }
 

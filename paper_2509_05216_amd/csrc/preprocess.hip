@@ -263,7 +263,8 @@ __global__ __launch_bounds__(256) void k_preprocess_fwd(ParamsDev prm, ViewTable
                                                         float4* __restrict__ splat,
                                                         uint2* __restrict__ rect,
                                                         uint32_t* __restrict__ dkey,
-                                                        uint8_t* __restrict__ clampm) {
+                                                        uint8_t* __restrict__ clampm,
+                                                        int32_t* __restrict__ radii) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int n = prm.n;
   if (i >= n) return;
@@ -278,6 +279,7 @@ __global__ __launch_bounds__(256) void k_preprocess_fwd(ParamsDev prm, ViewTable
     Proj p;
     project_view(b, c, vt.tile, p);
     const size_t o = (size_t)v * n + i;
+    if (radii != nullptr) radii[o] = p.radius;  // 0 unless touched
     if (!p.touched) {
       rect[o] = make_uint2(1u | (1u << 16), 0u);
       dkey[o] = 0xffffffffu;
@@ -757,11 +759,12 @@ gs_status launch_preprocess_fwd(const ParamsDev& p, const ViewTable& vt, Frame& 
   auto* rc = (uint2*)f.rect.p;
   auto* dk = (uint32_t*)f.dkey.p;
   auto* cm = (uint8_t*)f.clampm.p;
+  auto* rd = f.keep_radii ? (int32_t*)f.radii.p : nullptr;
   switch (p.sh_degree) {
-    case 0: hipLaunchKernelGGL(k_preprocess_fwd<0>, dim3(blocks), dim3(256), 0, s, p, vt, sp, rc, dk, cm); break;
-    case 1: hipLaunchKernelGGL(k_preprocess_fwd<1>, dim3(blocks), dim3(256), 0, s, p, vt, sp, rc, dk, cm); break;
-    case 2: hipLaunchKernelGGL(k_preprocess_fwd<2>, dim3(blocks), dim3(256), 0, s, p, vt, sp, rc, dk, cm); break;
-    default: hipLaunchKernelGGL(k_preprocess_fwd<3>, dim3(blocks), dim3(256), 0, s, p, vt, sp, rc, dk, cm); break;
+    case 0: hipLaunchKernelGGL(k_preprocess_fwd<0>, dim3(blocks), dim3(256), 0, s, p, vt, sp, rc, dk, cm, rd); break;
+    case 1: hipLaunchKernelGGL(k_preprocess_fwd<1>, dim3(blocks), dim3(256), 0, s, p, vt, sp, rc, dk, cm, rd); break;
+    case 2: hipLaunchKernelGGL(k_preprocess_fwd<2>, dim3(blocks), dim3(256), 0, s, p, vt, sp, rc, dk, cm, rd); break;
+    default: hipLaunchKernelGGL(k_preprocess_fwd<3>, dim3(blocks), dim3(256), 0, s, p, vt, sp, rc, dk, cm, rd); break;
   }
   GS_LAUNCHED("preprocess_fwd");
   return GS_OK;
@@ -815,26 +818,6 @@ gs_status launch_preprocess_bwd(const ParamsDev& p, const ViewTable& vt, Frame& 
 //   normals (r cos theta, r sin theta).
 namespace isogs {
 namespace {
-
-__device__ inline void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
-#pragma unroll
-  for (int r = 0; r < 10; ++r) {
-    if (r > 0) {
-      k0 += 0x9E3779B9u;
-      k1 += 0xBB67AE85u;
-    }
-    const uint64_t p0 = (uint64_t)0xD2511F53u * c[0];
-    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c[2];
-    const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c[1] ^ k0;
-    const uint32_t n1 = (uint32_t)p1;
-    const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c[3] ^ k1;
-    const uint32_t n3 = (uint32_t)p0;
-    c[0] = n0;
-    c[1] = n1;
-    c[2] = n2;
-    c[3] = n3;
-  }
-}
 
 __device__ inline float u24(uint32_t x) { return (float)(x >> 8) * (1.0f / 16777216.0f); }
 

@@ -9,6 +9,8 @@ from .core import (Context, Frame, Params, adam_step, bw_probe, camera, camera_f
 from .autograd import RasterizeFn, rasterize  # noqa: F401
 from .batched import StepGraph, autotune  # noqa: F401
 from .serve import Server  # noqa: F401
+from .train import Schedule, Trainer  # noqa: F401
+from . import density  # noqa: F401
 from .core import LONGEST_FIRST, PERSISTENT  # noqa: F401
 
 __all__ = ["Context", "Frame", "Params", "IsogsError", "adam_step", "camera",

@@ -486,6 +486,43 @@ gs_status gs_densify(gs_ctx* ctx, gs_params p, gs_params m, gs_params v,
 gs_status gs_opacity_reset(gs_ctx* ctx, gs_params p, gs_params m, gs_params v,
                            double max_opacity, void* stream);
 
+/* ------------------------------------------- isosurface points and targets
+ * The extraction and target rendering that Sec. III (Method Overview) does
+ * with ParaView, on a volume already in device memory (the in-situ direction
+ * of Sec. V).  volume: values[k][j][i] (device float32, caller-owned) at the
+ * vertices of an nx x ny x nz grid over the box [lo, hi] (vertex (i, j, k) at
+ * lo + (i, j, k) h, h = (hi - lo) / (n - 1)); each side 2 .. 2^20. */
+typedef struct {
+  const float* values;
+  int64_t nx, ny, nz;
+  float lo[3], hi[3];
+} gs_volume;
+
+/* Isosurface points: every grid edge whose end values lie strictly on both
+ * sides of iso gives the point p0 + t (p1 - p0), t = (v0 - iso) / (v0 - v1)
+ * (the vertex rule of marching cubes), in canonical order (vertices
+ * row-major in (k, j, i), per vertex its +x, +y, +z edges).  A crossing on
+ * edge e = 3 vertex + axis is kept when the Philox4x32-10 uniform
+ * (x0 >> 8) 2^-24 of counter (e low, e high, 3, 0), key (seed low, seed
+ * high), is below keep_prob (1: all).  *n_points receives the number kept;
+ * with xyz (device float32 [3][capacity]) non-NULL they are written there
+ * (GS_ERR_CAPACITY, nothing written, if they do not fit).  Synchronises
+ * `stream` once (the count is read back). */
+gs_status gs_iso_extract(gs_ctx* ctx, gs_volume volume, float iso, float keep_prob,
+                         uint64_t seed, float* xyz, int64_t capacity, int64_t* n_points,
+                         void* stream);
+
+/* Ray-cast target views of the isosurface: per pixel the ray from the camera
+ * centre through the pixel centre, clipped to the box, sampled every `step`
+ * (world units) with the trilinear interpolant; the first rise from below iso
+ * to at least iso is refined by ten bisections and shaded albedo(p) (0.2 +
+ * 0.8 |n . d|), n the interpolant's normalised gradient, albedo = (0.85,
+ * 0.45 + 0.25 z, 0.30 + 0.25 (x + 1)); misses are black.  images[v]: device
+ * float32 [3][H][W].  step > 0 and >= 1e-5 of the box diagonal.  Float64
+ * arithmetic.  Asynchronous. */
+gs_status gs_raycast(gs_ctx* ctx, gs_volume volume, float iso, const gs_camera* cams,
+                     int32_t n_views, float step, float* const* images, void* stream);
+
 /* -------------------------------------------------------------- autotuner
  * Times forward + backward of the given views for tile sizes {8, 16, 32},
  * LDS depths {32, 64, 128, 256} and the grid or persistent longest-first

@@ -109,6 +109,11 @@ class GsDensityInfo(C.Structure):
                 ("pruned", C.c_int64)]
 
 
+class GsVolume(C.Structure):
+    _fields_ = [("values", C.c_void_p), ("nx", C.c_int64), ("ny", C.c_int64), ("nz", C.c_int64),
+                ("lo", C.c_float * 3), ("hi", C.c_float * 3)]
+
+
 class GsTuneEntry(C.Structure):
     _fields_ = [("tile", C.c_int32), ("lds_depth", C.c_int32), ("flags", C.c_int32),
                 ("ms", C.c_float)]
@@ -141,6 +146,10 @@ SIGNATURES = [
                              C.POINTER(GsDensityOpts), GsParams, GsParams, GsParams, _P,
                              C.POINTER(GsDensityInfo), _P]),
     ("gs_opacity_reset", C.c_int, [_P, GsParams, GsParams, GsParams, C.c_double, _P]),
+    ("gs_iso_extract", C.c_int, [_P, GsVolume, C.c_float, C.c_float, C.c_uint64, _P, C.c_int64,
+                                 C.POINTER(C.c_int64), _P]),
+    ("gs_raycast", C.c_int, [_P, GsVolume, C.c_float, C.POINTER(GsCamera), C.c_int32,
+                             C.c_float, _PP, _P]),
     ("gs_adam_step", C.c_int, [_P, GsParams, GsParams, GsParams, GsParams,
                                C.POINTER(GsAdamOpts), C.c_int64, _P]),
     ("gs_bw_probe", C.c_int, [_P, _P, _P, C.c_size_t, _P]),

@@ -19,7 +19,8 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libisogs.so")
 SOURCES = ["api.hip", "preprocess.hip", "sort.hip", "blend.hip", "loss.hip", "adam.hip", "graph.hip",
-           "probe.hip", "serve.hip", "density.hip"]
+           "probe.hip", "serve.hip", "density.hip",
+           "iso.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

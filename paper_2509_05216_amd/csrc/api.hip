@@ -334,6 +334,9 @@ static void ctx_free(gs_ctx* ctx) {
   buf_free(ctx, ctx->dens_blk);
   if (ctx->dens_host != nullptr) (void)hipHostFree(ctx->dens_host);
   ctx->dens_host = nullptr;
+  buf_free(ctx, ctx->iso_blk);
+  if (ctx->iso_host != nullptr) (void)hipHostFree(ctx->iso_host);
+  ctx->iso_host = nullptr;
   (void)timing_collect(ctx);
   for (int i = 0; i < ctx->n_free; ++i) (void)hipEventDestroy(ctx->free_events[i]);
   delete[] ctx->free_events;
@@ -1016,6 +1019,80 @@ gs_status gs_densify(gs_ctx* ctx, gs_params p, gs_params m, gs_params v, gs_dens
   StageTimer tm(ctx, ST_DENSIFY, (hipStream_t)stream);
   return densify_run(ctx, p, m, v, stats, o, write ? &p_out : nullptr, write ? &m_out : nullptr,
                      write ? &v_out : nullptr, src_index, info, (hipStream_t)stream);
+}
+
+static bool valid_volume(const gs_volume& v, const char* what) {
+  if (v.values == nullptr) {
+    set_error("%s: volume values are null", what);
+    return false;
+  }
+  if (v.nx < 2 || v.ny < 2 || v.nz < 2 || v.nx > (1 << 20) || v.ny > (1 << 20) ||
+      v.nz > (1 << 20) || (double)v.nx * v.ny * v.nz > 1.2e11) {
+    set_error("%s: volume of %lld x %lld x %lld vertices (each side 2 .. 2^20)", what,
+              (long long)v.nx, (long long)v.ny, (long long)v.nz);
+    return false;
+  }
+  for (int a = 0; a < 3; ++a)
+    if (!(v.hi[a] > v.lo[a])) {
+      set_error("%s: empty volume box along axis %d", what, a);
+      return false;
+    }
+  return true;
+}
+
+gs_status gs_iso_extract(gs_ctx* ctx, gs_volume vol, float iso, float keep_prob, uint64_t seed,
+                         float* xyz, int64_t capacity, int64_t* n_points, void* stream) {
+  if (ctx == nullptr || n_points == nullptr) {
+    set_error("gs_iso_extract: null argument");
+    return GS_ERR_INVALID;
+  }
+  if (!valid_volume(vol, "gs_iso_extract")) return GS_ERR_INVALID;
+  if (!(keep_prob >= 0.f && keep_prob <= 1.f) || !(iso == iso)) {
+    set_error("gs_iso_extract: keep_prob %g not in [0, 1] or iso is NaN", (double)keep_prob);
+    return GS_ERR_INVALID;
+  }
+  if (xyz != nullptr && capacity < 1) {
+    set_error("gs_iso_extract: capacity %lld < 1", (long long)capacity);
+    return GS_ERR_INVALID;
+  }
+  gs_status st = set_device(ctx);
+  if (st != GS_OK) return st;
+  return iso_extract_run(ctx, vol, iso, keep_prob, seed, xyz, capacity, n_points,
+                         (hipStream_t)stream);
+}
+
+gs_status gs_raycast(gs_ctx* ctx, gs_volume vol, float iso, const gs_camera* cams,
+                     int32_t n_views, float step, float* const* images, void* stream) {
+  if (ctx == nullptr || cams == nullptr || images == nullptr) {
+    set_error("gs_raycast: null argument");
+    return GS_ERR_INVALID;
+  }
+  if (!valid_volume(vol, "gs_raycast")) return GS_ERR_INVALID;
+  if (n_views < 1 || n_views > kMaxViews) {
+    set_error("gs_raycast: n_views %d not in [1, %d]", n_views, kMaxViews);
+    return GS_ERR_INVALID;
+  }
+  double diag = 0.0;
+  for (int a = 0; a < 3; ++a) {
+    const double e = (double)vol.hi[a] - (double)vol.lo[a];
+    diag += e * e;
+  }
+  diag = std::sqrt(diag);
+  if (!(step > 0.f) || diag / (double)step > 1e5) {
+    set_error("gs_raycast: step %g must be positive and at least 1e-5 of the box diagonal",
+              (double)step);
+    return GS_ERR_INVALID;
+  }
+  for (int v = 0; v < n_views; ++v) {
+    if (!valid_camera(cams[v], v)) return GS_ERR_INVALID;
+    if (images[v] == nullptr) {
+      set_error("gs_raycast: images[%d] is null", v);
+      return GS_ERR_INVALID;
+    }
+  }
+  gs_status st = set_device(ctx);
+  if (st != GS_OK) return st;
+  return launch_raycast(vol, iso, cams, n_views, images, (double)step, (hipStream_t)stream);
 }
 
 gs_status gs_opacity_reset(gs_ctx* ctx, gs_params p, gs_params m, gs_params v,

@@ -154,6 +154,8 @@ struct Ctx {
   struct LossScratch* loss_scratch = nullptr;  // workspace of eager gs_loss_grad calls
   DevBuf dens_blk;                 // gs_densify: block totals and offsets
   uint32_t* dens_host = nullptr;   // gs_densify: pinned read-back of the totals
+  DevBuf iso_blk;                  // gs_iso_extract: block totals and offsets
+  unsigned long long* iso_host = nullptr;  // gs_iso_extract: pinned read-back of the count
   // set while a graph is being captured: no allocation, no stage events
   bool capturing = false;
   // stage timing
@@ -327,6 +329,12 @@ gs_status loss_noalloc_workspace(int device, const int* W, const int* H, int nv,
 gs_status launch_loss(const LossScratch& ls, const float* const* x, const float* const* y,
                       const int* W, const int* H, int nv, float lambda, float* loss_out,
                       float* const* dl, hipStream_t s);
+// iso.hip
+gs_status iso_extract_run(Ctx* ctx, const gs_volume& vol, float iso, float keep_prob,
+                          uint64_t seed, float* xyz, int64_t cap, int64_t* n_kept,
+                          hipStream_t s);
+gs_status launch_raycast(const gs_volume& vol, float iso, const gs_camera* cams, int nv,
+                         float* const* images, double step, hipStream_t s);
 // density.hip
 gs_status launch_density_accumulate(const Frame& f, const gs_density_stats& st, float scale,
                                     hipStream_t s);

@@ -83,6 +83,8 @@ def parse():
     ap.add_argument("--cpu-tiles", type=int, default=320, help="tiles in the CPU-baseline sample")
     ap.add_argument("--only", choices=["all", "batched", "plain"], default="all")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-train", action="store_true", help="skip the 1M-Gaussian training run")
+    ap.add_argument("--train-iters", type=int, default=500)
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--workload", choices=["kingsnake4m", "miranda18m"], default="kingsnake4m",
                     help="kingsnake4m: 4M Gaussians, 2x2048^2 + 2x1536^2 batched and 2048^2 plain "
@@ -254,6 +256,80 @@ def serve_bench(P, ctx, params4m, torch, n_requests=2000, rate=200.0):
     for s in scenes[:2]:
         del s
     return res
+
+
+def train_c1(P, ctx, torch, iters=500, n_target=1_000_000, G=512, res=1024, n_views=128,
+             n_held=16, seed=1001):
+    """The 1M-Gaussian training run, in situ on the device: the seeded 512^3 blob +
+    noise volume, its isosurface points (subsampled to about 1M by the keep rule),
+    Gaussians initialised from them (SH3 N(0, 0.1), log-scales U(-5, -3), random
+    rotations, opacity logit 0.1), ray-cast targets of a 128-view 1024^2 orbit,
+    500 iterations of L1 + SSIM with density control every 100 iterations from
+    iteration 200 to 400; PSNR / SSIM on 16 held-out views (another orbit) every 100."""
+    import gsscenes
+    from paper_2509_05216_amd import iso
+    from paper_2509_05216_amd.train import Schedule, Trainer
+    out = {}
+    t0 = time.perf_counter()
+    field, _ = gsscenes.make_field("iso1m")
+    vol = iso.Volume(gsscenes.sample_volume(field, G, device="cuda"))
+    torch.cuda.synchronize()
+    out["volume_s"] = round(time.perf_counter() - t0, 2)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    ev[0].record()
+    m = iso.count(ctx, vol)
+    ev[1].record()
+    pts = iso.extract(ctx, vol, 0.5, min(1.0, n_target / m), seed)
+    params = P.init_from_points(ctx, pts.contiguous(), 3, log_scale_range=(-5.0, -3.0),
+                                random_quats=True, opacity_logit=0.1, sh_std=0.1, seed=seed)
+    ev[2].record()
+    h = 2.0 / (G - 1)
+    cams = P.orbit_cameras(n_views, 2.5, 60.0, res, res)
+    held = P.orbit_cameras(n_held + 1, 2.5, 60.0, res, res)[1:]
+    targets = []
+    for i in range(0, n_views, 16):
+        targets += iso.raycast(ctx, vol, cams[i:i + 16], 0.5, h)
+    refs = iso.raycast(ctx, vol, held, 0.5, h)
+    ev[3].record()
+    torch.cuda.synchronize()
+    out.update(crossings=m, gaussians=pts.shape[1],
+               extract_ms=round(ev[0].elapsed_time(ev[1]) + ev[1].elapsed_time(ev[2]), 3),
+               raycast_ms=round(ev[2].elapsed_time(ev[3]), 2),
+               raycast_mpix_per_s=round((n_views + n_held) * res * res /
+                                        (ev[2].elapsed_time(ev[3]) * 1e-3) / 1e6, 1))
+    del vol
+    sched = Schedule(densify_from=100, densify_until=450, densify_interval=100,
+                     opacity_reset_interval=3000, extent=2.5, seed=seed)
+    tr = Trainer(ctx, params, cams, targets, schedule=sched, seed=seed)
+    curve = [{"it": 0, **{k: round(v, 4) for k, v in tr.evaluate(held, refs).items()
+                          if k != "per_view"}}]
+    t1 = time.perf_counter()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    loss_curve = []
+    train_ms = 0.0
+    for blk in range(iters // 100):
+        e0.record()
+        tr.run(100, log_every=10)
+        e1.record()
+        torch.cuda.synchronize()
+        train_ms += e0.elapsed_time(e1)
+        ev_ = tr.evaluate(held, refs)
+        curve.append({"it": tr.it, "n": tr.params.n,
+                      **{k: round(v, 4) for k, v in ev_.items() if k != "per_view"}})
+    out["wall_s"] = round(time.perf_counter() - t1, 2)
+    out["ms_per_iteration"] = round(train_ms / iters, 3)
+    out["loss_every_10"] = [round(r["loss"], 5) for r in tr.history if "loss" in r
+                            and r["it"] % 10 == 0]
+    out["densify"] = [{"it": r["it"], **{k: r["densify"][k] for k in ("n_in", "n_out", "cloned",
+                                                                      "split", "pruned")}}
+                      for r in tr.history if "densify" in r]
+    out["held_out"] = curve
+    out["workload"] = (f"seeded {G}^3 blob+noise volume on the device, {pts.shape[1]} Gaussians "
+                       f"from its isosurface, {n_views}-view {res}^2 orbit (ray-cast targets), "
+                       f"{iters} iterations L1+SSIM, density control at 200/300/400, "
+                       f"{n_held} held-out views")
+    tr.close()
+    return out
 
 
 def frame_counts(frame, n, torch):
@@ -564,6 +640,11 @@ def main():
         "hbm_probe": {"GBps": round(probe_gbs, 1), "bytes_per_launch": 2 * probe_bytes,
                       "ms": round(probe_ms, 4), "frac_of_peak": round(probe_gbs / HBM_PEAK_GBS, 4)},
     }
+    if not args.no_train and args.workload == "kingsnake4m":
+        t0 = time.perf_counter()
+        out["train_c1"] = train_c1(P, ctx, torch, iters=args.train_iters)
+        log(f"training run in {time.perf_counter() - t0:.1f}s: "
+            f"{out['train_c1']['held_out'][-1]}")
     if not args.no_serve:
         out["serve"] = serve_bench(P, ctx, params, torch, n_requests=args.serve_requests)
     if not args.no_cpu_baseline:

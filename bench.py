@@ -80,7 +80,6 @@ def parse():
     ap.add_argument("--tile", type=int, default=16)
     ap.add_argument("--lds-depth", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-tiles", type=int, default=320, help="tiles in the CPU-baseline sample")
     ap.add_argument("--only", choices=["all", "batched", "plain"], default="all")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-train", action="store_true", help="skip the 1M-Gaussian training run")
@@ -383,29 +382,130 @@ def roofline(stages, steps, n, views, visible, K, pixels, pairs, traffic=None):
                  "avg_ms": round(avg_ms, 4), "algorithmic_bytes": byts}
 
 
-def cpu_baseline(scene, cam_d, target, n_tiles, tile=16):
-    """The oracle's fwd+bwd on a bounded sample of one 2048^2 view (single thread).
+# ---------------------------------------------------------------- CPU baseline
+# The oracle (float64 numpy, as it stands) on the host's cores: per-Gaussian
+# stages split into chunks over threads (numpy releases the GIL in its loops),
+# per-tile stages and whole views over forked worker processes that inherit the
+# projection.  BLAS stays single-threaded inside each worker.
+_CPU = {}
 
-    Per-Gaussian work (projection, parameter chain rule) runs on all N; the
-    per-tile work (binning, compositing forward and backward) on a seeded
-    sample of tiles, scaled by its share of the total list length; the loss
-    on a 256^2 crop, scaled by pixel count.
-    """
+
+def _cpu_cores():
+    return max(1, min(len(os.sched_getaffinity(0)), 16))
+
+
+def _chunked(fn, n, cores):
+    """fn(a, b) over `cores` contiguous chunks of range(n), on threads."""
+    import concurrent.futures as cf
+    bounds = np.linspace(0, n, cores + 1).astype(np.int64)
+    with cf.ThreadPoolExecutor(max_workers=cores) as ex:
+        return list(ex.map(lambda i: fn(int(bounds[i]), int(bounds[i + 1])), range(cores)))
+
+
+def _slice_params(params, a, b):
+    return {k: (v[..., a:b] if isinstance(v, np.ndarray) else v) for k, v in params.items()}
+
+
+def _merge(parts):
+    out = {}
+    for k, v in parts[0].items():
+        if isinstance(v, np.ndarray) and v.ndim >= 1:
+            out[k] = np.concatenate([p[k] for p in parts], axis=v.ndim - 1)
+        else:
+            out[k] = v
+    return out
+
+
+def _tile_worker(tiles):
+    from oracle import blend
+    pr, W, H, tile, target = _CPU["pr"], _CPU["W"], _CPU["H"], _CPU["tile"], _CPU["target"]
+    tx = (W + tile - 1) // tile
+    rect, touched, bits = pr["rect"], pr["touched"], pr["depth32"].view(np.uint32)
+    n = pr["m"].shape[1]
+    acc = dict(m=np.zeros((2, n)), conic=np.zeros((3, n)), opacity=np.zeros(n),
+               rgb=np.zeros((3, n)))
+    for t in tiles:
+        x, y = t % tx, t // tx
+        members = np.nonzero(touched & (rect[0] <= x) & (x <= rect[2]) & (rect[1] <= y)
+                             & (y <= rect[3]))[0]
+        g = members[np.argsort(bits[members], kind="stable")]
+        X, Y = blend.tile_pixels(x, y, tile, W, H)
+        blend.composite_tile(pr, g, X + 0.5, Y + 0.5, (0, 0, 0))
+        d = np.asarray(target[:, Y, X], np.float64) * 1e-3
+        blend.backward_tile(pr, g, X + 0.5, Y + 0.5, d, (0, 0, 0), acc)
+    return acc
+
+
+def _loss_worker(cells):
+    from oracle import loss as oloss
+    target, c = _CPU["target"], _CPU["cell"]
+    for (y0, x0) in cells:
+        crop = np.asarray(target[:, y0:y0 + c, x0:x0 + c], np.float64)
+        oloss.view_loss(crop * 0.9, crop)
+        oloss.view_loss_grad(crop * 0.9, crop)
+    return len(cells)
+
+
+def _view_worker(k):
+    from oracle import loss as oloss
+    from oracle import pipeline
+    params, cams, targets = _CPU["params"], _CPU["cams"], _CPU["targets"]
+    f = pipeline.forward_view(params, cams[k], 16)
+    L = oloss.view_loss(f["image"], targets[k]) / len(cams)
+    d = oloss.view_loss_grad(f["image"], targets[k]) / len(cams)
+    _, g = pipeline.backward_view(params, cams[k], f, d)
+    return L, g
+
+
+def cpu_c0_full(cores):
+    """The whole oracle fwd + loss + bwd of the 10k-Gaussian scene over its 8 views of
+    256^2 (one view per worker process)."""
+    import multiprocessing as mp
+
+    import gsscenes
+    from oracle import camera as ocam
+    scene = gsscenes.make_scene("tiny")
+    cams = [ocam.to_float32(c) for c in ocam.orbit_cameras(8, 2.5, 60.0, 256, 256)]
+    targets = make_targets(scene, cams, coarse=128)
+    _CPU.update(params=scene.params, cams=cams, targets=targets)
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(min(cores, len(cams))) as pool:
+        res = pool.map(_view_worker, range(len(cams)))
+    dt = time.perf_counter() - t0
+    _CPU.clear()
+    return {"mpix_per_s": round(8 * 256 * 256 / dt / 1e6, 6), "seconds": round(dt, 2),
+            "loss": round(float(sum(r[0] for r in res)), 6),
+            "processes": min(cores, len(cams)),
+            "sample": "full run: 10k Gaussians, 8 views of 256^2, fwd + L1/SSIM + bwd"}
+
+
+def cpu_baseline(scene, cam_d, target, tile_frac=1 / 64, tile=16):
+    """The oracle's fwd+bwd on one 2048^2 view of the 4M scene on the host's cores:
+    projection and parameter backward on all Gaussians (threads over chunks),
+    binning + compositing fwd/bwd on a seeded 1/64 of the tiles (processes), scaled
+    by that sample's share of the total list length; the loss over the whole view;
+    plus the full 10k-Gaussian 8-view run."""
+    import multiprocessing as mp
+
     from threadpoolctl import threadpool_limits
 
-    from oracle import blend, loss as oloss, project, backward as obwd
+    from oracle import backward as obwd
+    from oracle import project
+    cores = _cpu_cores()
+    params = scene.params
+    n = params["means"].shape[1]
+    W, H = cam_d["width"], cam_d["height"]
+    tx, ty = (W + tile - 1) // tile, (H + tile - 1) // tile
     with threadpool_limits(limits=1):
-        params = scene.params
-        W, H = cam_d["width"], cam_d["height"]
-        tx, ty = (W + tile - 1) // tile, (H + tile - 1) // tile
         t0 = time.perf_counter()
-        pr = project.project(params, cam_d, tile)
+        parts = _chunked(lambda a, b: project.project(_slice_params(params, a, b), cam_d, tile),
+                         n, cores)
+        pr = _merge(parts)
         t_proj = time.perf_counter() - t0
         rng = np.random.default_rng(1234)
-        sample = rng.choice(tx * ty, size=min(n_tiles, tx * ty), replace=False)
-        rect = pr["rect"]
-        touched = pr["touched"]
-        # total list length of every tile (for scaling) from the rectangles
+        n_tiles = max(1, int(round(tx * ty * tile_frac)))
+        sample = rng.choice(tx * ty, size=n_tiles, replace=False)
+        rect, touched = pr["rect"], pr["touched"]
         cnt = np.zeros((ty + 1, tx + 1), np.int64)
         ids = np.nonzero(touched)[0]
         np.add.at(cnt, (rect[1, ids], rect[0, ids]), 1)
@@ -413,40 +513,43 @@ def cpu_baseline(scene, cam_d, target, n_tiles, tile=16):
         np.add.at(cnt, (rect[3, ids] + 1, rect[0, ids]), -1)
         np.add.at(cnt, (rect[3, ids] + 1, rect[2, ids] + 1), 1)
         lens = np.cumsum(np.cumsum(cnt, 0), 1)[:ty, :tx].ravel()
-        n = params["means"].shape[1]
-        acc = dict(m=np.zeros((2, n)), conic=np.zeros((3, n)), opacity=np.zeros(n),
-                   rgb=np.zeros((3, n)))
-        bits = pr["depth32"].view(np.uint32)
+        _CPU.update(pr=pr, W=W, H=H, tile=tile, target=target)
         t0 = time.perf_counter()
-        for t in sample:
-            x, y = t % tx, t // tx
-            members = np.nonzero(touched & (rect[0] <= x) & (x <= rect[2]) & (rect[1] <= y)
-                                 & (y <= rect[3]))[0]
-            g = members[np.argsort(bits[members], kind="stable")]
-            X, Y = blend.tile_pixels(x, y, tile, W, H)
-            blend.composite_tile(pr, g, X + 0.5, Y + 0.5, (0, 0, 0))
-            d = np.asarray(target[:, Y, X], np.float64) * 1e-3
-            blend.backward_tile(pr, g, X + 0.5, Y + 0.5, d, (0, 0, 0), acc)
+        with mp.get_context("fork").Pool(cores) as pool:
+            accs = pool.map(_tile_worker, [list(c) for c in np.array_split(sample, cores)])
         t_tiles = time.perf_counter() - t0
+        _CPU.clear()
+        acc = {k: sum(a[k] for a in accs) for k in accs[0]}
         share = lens[sample].sum() / max(lens.sum(), 1)
         t0 = time.perf_counter()
-        obwd.param_grads(pr, params, cam_d, acc)
+        bounds = np.linspace(0, n, cores + 1).astype(np.int64)
+        _chunked(lambda a, b: obwd.param_grads(
+            parts[int(np.searchsorted(bounds, a))], _slice_params(params, a, b), cam_d,
+            {k: v[..., a:b] for k, v in acc.items()}), n, cores)
         t_pbwd = time.perf_counter() - t0
-        crop = np.asarray(target[:, :256, :256], np.float64)
+        # the loss and its gradient over the whole view, as 256^2 cells over the processes
+        cells = [(y, x) for y in range(0, H, 256) for x in range(0, W, 256)]
+        _CPU.update(target=target, cell=256)
         t0 = time.perf_counter()
-        oloss.view_loss(crop * 0.9, crop)
-        oloss.view_loss_grad(crop * 0.9, crop)
-        t_loss = (time.perf_counter() - t0) * (W * H) / (256 * 256)
+        with mp.get_context("fork").Pool(cores) as pool:
+            pool.map(_loss_worker, [cells[i::cores] for i in range(cores)])
+        t_loss = time.perf_counter() - t0
+        _CPU.clear()
     total = t_proj + t_pbwd + t_tiles / max(share, 1e-12) + t_loss
-    return {"value": round(W * H / total / 1e6, 6), "unit": "Mpix/s", "cores": 1,
+    c0 = cpu_c0_full(cores)
+    return {"value": round(W * H / total / 1e6, 6), "unit": "Mpix/s", "cores": cores,
             "kind": "oracle",
-            "sample": (f"one {W}x{H} view of the {n}-Gaussian scene, float64 numpy, 1 thread: "
-                       f"projection and parameter backward on all Gaussians, binning + "
-                       f"compositing fwd/bwd on {len(sample)} seeded tiles scaled by their "
-                       f"{share:.4f} share of list length, loss on a 256^2 crop scaled by "
-                       f"pixels (estimate)"),
-            "seconds": round(t_proj + t_tiles + t_pbwd + t_loss / ((W * H) / (256 * 256)), 2),
-            "est_seconds_full_view": round(total, 1)}
+            "sample": (f"one {W}x{H} view of the {n}-Gaussian scene, float64 numpy on {cores} "
+                       f"cores: projection and parameter backward on all Gaussians ({cores} "
+                       f"threads over chunks), binning + compositing fwd/bwd on {n_tiles} seeded "
+                       f"tiles (1/64 of the view; {cores} processes) scaled by their "
+                       f"{share:.4f} share of list length (estimate), L1+SSIM loss and gradient "
+                       f"over the whole view as 256^2 cells ({cores} processes)"),
+            "seconds": round(t_proj + t_tiles + t_pbwd + t_loss, 2),
+            "est_seconds_full_view": round(total, 1),
+            "stages_s": {"project": round(t_proj, 2), "tiles_sample": round(t_tiles, 2),
+                         "param_bwd": round(t_pbwd, 2), "loss": round(t_loss, 2)},
+            "c0_full": c0}
 
 
 def main():
@@ -649,8 +752,7 @@ def main():
         out["serve"] = serve_bench(P, ctx, params, torch, n_requests=args.serve_requests)
     if not args.no_cpu_baseline:
         t0 = time.perf_counter()
-        out["cpu_baseline"] = cpu_baseline(scene, cams_d[0], targets_np[0], args.cpu_tiles,
-                                           args.tile)
+        out["cpu_baseline"] = cpu_baseline(scene, cams_d[0], targets_np[0], tile=args.tile)
         log(f"cpu baseline in {time.perf_counter() - t0:.1f}s")
     print(json.dumps(out), flush=True)
 

@@ -83,6 +83,7 @@ def parse():
     ap.add_argument("--only", choices=["all", "batched", "plain"], default="all")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-train", action="store_true", help="skip the 1M-Gaussian training run")
+    ap.add_argument("--no-c3", action="store_true", help="skip the in-situ 18M-Gaussian 4096^2 step")
     ap.add_argument("--train-iters", type=int, default=500)
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--workload", choices=["kingsnake4m", "miranda18m"], default="kingsnake4m",
@@ -328,6 +329,69 @@ def train_c1(P, ctx, torch, iters=500, n_target=1_000_000, G=512, res=1024, n_vi
                        f"{iters} iterations L1+SSIM, density control at 200/300/400, "
                        f"{n_held} held-out views")
     tr.close()
+    return out
+
+
+def miranda_insitu(P, torch, steps, warmup, n_target=18_000_000, G=2048, res=4096, seed=1003):
+    """The 18M-Gaussian workload built in situ on the device and timed: the seeded
+    2048^3 mixing-layer volume (34 GB, slab by slab on the device), its isosurface
+    points subsampled to about 18M by the keep rule, Gaussians initialised from them
+    (log-scales log h +- 0.5, random rotations, SH3 N(0, 0.1), opacity logit 0.1),
+    ray-cast targets of two 4096^2 orbit views; then the batched step (autotuned,
+    captured in a graph) on its own context, with the peak device memory."""
+    import gsscenes
+    from paper_2509_05216_amd import iso
+    out = {}
+    ctx = P.Context(0)
+    t0 = time.perf_counter()
+    field, _ = gsscenes.make_field("miranda18m")
+    vol = iso.Volume(gsscenes.sample_volume(field, G, device="cuda", progress=log))
+    torch.cuda.synchronize()
+    out["volume_s"] = round(time.perf_counter() - t0, 2)
+    out["volume_bytes"] = vol.values.numel() * 4
+    h = 2.0 / (G - 1)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    ev[0].record()
+    m = iso.count(ctx, vol)
+    pts = iso.extract(ctx, vol, 0.5, min(1.0, n_target / m), seed)
+    params = P.init_from_points(ctx, pts.contiguous(), 3, log_scale=float(np.log(h)),
+                                log_scale_jitter=0.5, random_quats=True, opacity_logit=0.1,
+                                sh_std=0.1, seed=seed)
+    ev[1].record()
+    all_cams = P.orbit_cameras(16, 2.5, 60.0, res, res)
+    cams = [all_cams[0], all_cams[8]]
+    targets = [t.clone() for t in iso.raycast(ctx, vol, cams, 0.5, 2 * h)]
+    ev[2].record()
+    torch.cuda.synchronize()
+    out.update(crossings=m, gaussians=params.n,
+               extract_init_ms=round(ev[0].elapsed_time(ev[1]), 2),
+               raycast_ms=round(ev[1].elapsed_time(ev[2]), 2))
+    del vol, pts
+    torch.cuda.empty_cache()
+    torch.cuda.reset_peak_memory_stats()
+    log(f"18M scene in situ: {params.n} Gaussians from {m} crossings, "
+        f"{time.perf_counter() - t0:.1f}s")
+    best, table = P.autotune(ctx, params, cams, reps=3, use_cache=False, cache=None)
+    gtm, rec, cap, gloss = run_graph(P, ctx, params, cams, targets, steps, warmup, best, False,
+                                     torch)
+    pa = P.Params(*(t.clone() for t in params.tensors()), params.sh_degree)
+    atm, _, _, _ = run_graph(P, ctx, pa, cams, targets, steps, warmup, best, True, torch)
+    del pa
+    lib_now, lib_peak = ctx.memory()
+    free_b, total_b = torch.cuda.mem_get_info()
+    pix = 2 * res * res
+    out.update(
+        ms_per_step=round(gtm["median"], 3), ms_stats={k: round(v, 4) for k, v in gtm.items()},
+        mpix_per_s=round(pix / (gtm["median"] * 1e-3) / 1e6, 3),
+        gaussians_per_s=round(params.n * 2 / (gtm["median"] * 1e-3), 1),
+        ms_with_adam=round(atm["median"], 3), records_K=rec, capacity=cap, loss=round(gloss, 6),
+        autotune={"best": best, "table": sorted(table, key=lambda r: r["ms"])[:4]},
+        memory={"library_peak_bytes": lib_peak, "torch_peak_bytes": torch.cuda.max_memory_allocated(),
+                "device_used_bytes": total_b - free_b, "device_total_bytes": total_b},
+        workload=(f"miranda18m in situ: {params.n} Gaussians from the isosurface of a seeded "
+                  f"{G}^3 mixing-layer volume on the device, SH3, a batch of two {res}^2 views, "
+                  f"one hipGraph replay per step (tuned {best})"))
+    ctx.close()
     return out
 
 
@@ -750,6 +814,14 @@ def main():
             f"{out['train_c1']['held_out'][-1]}")
     if not args.no_serve:
         out["serve"] = serve_bench(P, ctx, params, torch, n_requests=args.serve_requests)
+    if not args.no_c3 and args.workload == "kingsnake4m":
+        del params
+        torch.cuda.empty_cache()
+        t0 = time.perf_counter()
+        c3 = miranda_insitu(P, torch, args.steps, args.warmup)
+        out["forms"]["miranda18m_batched_graph"] = c3
+        log(f"18M step: {c3['ms_per_step']:.2f} ms, {c3['mpix_per_s']:.0f} Mpix/s "
+            f"({time.perf_counter() - t0:.1f}s)")
     if not args.no_cpu_baseline:
         t0 = time.perf_counter()
         out["cpu_baseline"] = cpu_baseline(scene, cams_d[0], targets_np[0], tile=args.tile)

@@ -209,15 +209,50 @@ def serve_run(P, ctx, scene_params, requests, arrivals, outs, warm_cams, torch, 
     return st
 
 
+def train_for_serving(P, ctx, params, field_name, torch, iters=200, G=256, res=512, n_views=32,
+                      seed=7):
+    """A copy of `params` trained for `iters` iterations (L1 + SSIM, no density control)
+    on ray-cast 512^2 orbit views of its field's volume; returns it and the loss before /
+    after (the mean over the first and last ten iterations)."""
+    import gsscenes
+    from paper_2509_05216_amd import iso
+    from paper_2509_05216_amd.train import Trainer
+    field, _ = gsscenes.make_field(field_name)
+    vol = iso.Volume(gsscenes.sample_volume(field, G, device="cuda"))
+    cams = P.orbit_cameras(n_views, 2.5, 60.0, res, res)
+    targets = [t.clone() for t in iso.raycast(ctx, vol, cams[:16], 0.5, 2.0 / (G - 1))]
+    targets += [t.clone() for t in iso.raycast(ctx, vol, cams[16:], 0.5, 2.0 / (G - 1))]
+    del vol
+    p = P.Params(*(t.clone() for t in params.tensors()), params.sh_degree)
+    tr = Trainer(ctx, p, cams, targets, densify=False, seed=seed)
+    hist = tr.run(iters, log_every=1)
+    tr.close()
+    first = float(np.mean([h["loss"] for h in hist[:10]]))
+    last = float(np.mean([h["loss"] for h in hist[-10:]]))
+    return tr.params, round(first, 5), round(last, 5)
+
+
 def serve_bench(P, ctx, params4m, torch, n_requests=2000, rate=200.0):
-    """Three resident scenes (100k, 1M, 4M Gaussians, SH3); Poisson arrivals; sizes
-    512^2 / 1024^2 / 2048^2; batched server vs serial per-request rendering."""
+    """Three resident scenes (100k, 1M, 4M Gaussians, SH3), each first trained for 200
+    iterations on ray-cast views of its field; Poisson arrivals; sizes 512^2 / 1024^2 /
+    2048^2; servers batching across scenes and resolutions (4, 2 and 1 slots, up to 8
+    views per batch) vs serial per-request rendering."""
     import gsscenes
     t0 = time.perf_counter()
     s100k = gsscenes.make_scene("serve")
     s1m = gsscenes.make_scene("iso1m")
-    scenes = [P.Params.from_numpy(s100k.params), P.Params.from_numpy(s1m.params), params4m]
+    raw = [(P.Params.from_numpy(s100k.params), "serve"), (P.Params.from_numpy(s1m.params), "iso1m"),
+           (params4m, "kingsnake4m")]
     log(f"serve scenes in {time.perf_counter() - t0:.1f}s")
+    t0 = time.perf_counter()
+    scenes, training = [], []
+    for prm, fname in raw:
+        tp, l0, l1 = train_for_serving(P, ctx, prm, fname, torch)
+        scenes.append(tp)
+        training.append({"scene": fname, "gaussians": prm.n, "iterations": 200,
+                         "loss_first10": l0, "loss_last10": l1})
+    del raw
+    log(f"serve scenes trained in {time.perf_counter() - t0:.1f}s: {training}")
     arrivals, u_scene, u_size = gsscenes.arrival_times(rate, n_requests)
     sizes = [512, 1024, 2048]
     orbit = {s: P.orbit_cameras(64, 2.5, 60.0, s, s) for s in sizes}
@@ -229,8 +264,10 @@ def serve_bench(P, ctx, params4m, torch, n_requests=2000, rate=200.0):
     outs = {s: [(torch.empty((3, s, s), device="cuda"),) for _ in range(32)] for s in sizes}
     warm = {s: orbit[s][1] for s in sizes}
     pix = sum(next(iter(c)) ** 2 for _, c in requests)
-    res = {}
+    res = {"training": training}
     for name, opts in (("batched", dict(n_slots=4, max_batch_views=8)),
+                       ("batched_2slots", dict(n_slots=2, max_batch_views=8)),
+                       ("batched_1slot", dict(n_slots=1, max_batch_views=8)),
                        ("serial", dict(n_slots=1, max_batch_views=1))):
         st = serve_run(P, ctx, scenes, requests, arrivals, outs, warm, torch, **opts)
         res[name] = {"p50_ms": round(st["p50_ms"], 3), "p99_ms": round(st["p99_ms"], 3),
@@ -240,7 +277,7 @@ def serve_bench(P, ctx, params4m, torch, n_requests=2000, rate=200.0):
                      "deferred": st["deferred"], "peak_scratch_bytes": st["peak_bytes"],
                      "slots": opts["n_slots"], "max_batch_views": opts["max_batch_views"]}
         log(f"serve {name}: p50 {st['p50_ms']:.2f} ms, p99 {st['p99_ms']:.2f} ms, "
-            f"{st['mpix_per_s']:.0f} Mpix/s")
+            f"{st['mpix_per_s']:.0f} Mpix/s, {st['mean_batch_views']:.2f} views per batch")
     # saturation: the same requests submitted at once (offered load far above capacity)
     burst = [0.0] * min(600, n_requests)
     for name, opts in (("batched_saturated", dict(n_slots=4, max_batch_views=8)),
@@ -251,10 +288,10 @@ def serve_bench(P, ctx, params4m, torch, n_requests=2000, rate=200.0):
                      "mean_batch_views": round(st["mean_batch_views"], 2)}
         log(f"serve {name}: {st['mpix_per_s']:.0f} Mpix/s")
     res["workload"] = (f"{n_requests} requests, Poisson {rate:.0f}/s, scenes 100k/1M/4M "
-                       f"Gaussians (SH3) resident, sizes 512^2/1024^2/2048^2 uniform, "
+                       f"Gaussians (SH3, trained 200 iterations) resident, sizes "
+                       f"512^2/1024^2/2048^2 uniform, batches across scenes and sizes, "
                        f"{pix / 1e6:.0f} Mpix total")
-    for s in scenes[:2]:
-        del s
+    del scenes
     return res
 
 

@@ -217,6 +217,22 @@ gs_status gs_render_fwd(gs_ctx* ctx, gs_params params, const gs_camera* cams,
                         const gs_render_opts* opts, gs_frame** state,
                         void* stream);
 
+/* Forward render of n_views views (1..16) each of its own scene: params[v]
+ * (device SoA, caller-owned) is the scene of view v; views of the same scene
+ * (same parameter pointers) share one projection launch, and all views share
+ * one depth sort, one tile sort and one compositing launch.  Every view's
+ * image is bit-identical to rendering it alone (a view's tiles hold only its
+ * own records, in the same order).  For serving several resident scenes:
+ * forward only (gs_render_bwd, gs_density_accumulate and the per-(view,
+ * Gaussian) exports of such a frame return GS_ERR_UNSUPPORTED).  Inside the
+ * frame the views are grouped by scene (scenes in order of first
+ * appearance); the per-pixel exports follow that order.  opts->flags: only
+ * GS_RENDER_PERSISTENT and GS_RENDER_LONGEST_FIRST.  Synchronises `stream`
+ * once, as gs_render_fwd. */
+gs_status gs_render_fwd_multi(gs_ctx* ctx, const gs_params* params, const gs_camera* cams,
+                              int32_t n_views, float* const* images,
+                              const gs_render_opts* opts, gs_frame** state, void* stream);
+
 /* Training loss of n_views rendered images against targets and its image
  * gradient: mean over views of (1 - lambda) L1 + lambda (1 - SSIM), SSIM with
  * an 11x11 Gaussian window (sigma 1.5), C1 = 1e-4, C2 = 9e-4, zero padding.

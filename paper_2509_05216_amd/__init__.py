@@ -4,7 +4,7 @@ colour, tile binning and sort, alpha compositing, its backward, the loss
 gradient and Adam), behind the C ABI of include/isogs.h."""
 from ._lib import IsogsError, lib  # noqa: F401
 from .core import (Context, Frame, Params, adam_step, bw_probe, camera, camera_from_dict,  # noqa: F401
-                   camera_to_dict, init_from_points, loss_grad, loss_grad_into, orbit_cameras, render_bwd,
+                   camera_to_dict, init_from_points, loss_grad, loss_grad_into, orbit_cameras, render_bwd, render_fwd_multi,
                    render_fwd)
 from .autograd import RasterizeFn, rasterize  # noqa: F401
 from .batched import StepGraph, autotune  # noqa: F401

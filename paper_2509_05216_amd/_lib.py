@@ -135,6 +135,8 @@ SIGNATURES = [
                                       GsParams, _P]),
     ("gs_render_fwd", C.c_int, [_P, GsParams, C.POINTER(GsCamera), C.c_int32, _PP,
                                 C.POINTER(GsRenderOpts), C.POINTER(_P), _P]),
+    ("gs_render_fwd_multi", C.c_int, [_P, C.POINTER(GsParams), C.POINTER(GsCamera), C.c_int32,
+                                      _PP, C.POINTER(GsRenderOpts), C.POINTER(_P), _P]),
     ("gs_loss_grad", C.c_int, [_P, _PP, _PP, C.POINTER(GsCamera), C.c_int32, C.c_float, _P,
                                _PP, _P]),
     ("gs_loss_grad_noalloc", C.c_int, [_P, _PP, _PP, C.POINTER(GsCamera), C.c_int32,

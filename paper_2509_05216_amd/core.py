@@ -242,6 +242,30 @@ def render_fwd(ctx, params, cams, images=None, *, tile=16, lds_depth=256, bg=(0.
     return images, frame
 
 
+def render_fwd_multi(ctx, params_per_view, cams, images=None, *, tile=16, lds_depth=256,
+                     bg=(0.0, 0.0, 0.0), flags=0, frame=None, stream=None):
+    """Render view v of scene params_per_view[v] (views of several scenes in one
+    forward); returns (images, frame).  Forward only."""
+    if len(params_per_view) != len(cams):
+        raise ValueError("one parameter set per camera")
+    dev = params_per_view[0].means.device
+    if images is None:
+        images = [torch.empty((3, c.height, c.width), dtype=torch.float32, device=dev)
+                  for c in cams]
+    for img, c in zip(images, cams):
+        if tuple(img.shape) != (3, c.height, c.width) or not img.is_contiguous() \
+                or img.dtype != torch.float32:
+            raise ValueError("image tensors must be contiguous float32 (3, H, W)")
+    frame = frame if frame is not None else Frame()
+    pa, keep = L.ptr_array([i.data_ptr() for i in images])
+    parr = (L.GsParams * len(cams))(*[p.abi() for p in params_per_view])
+    o = _opts(tile, lds_depth, bg, flags)
+    L.check(L.lib().gs_render_fwd_multi(ctx.handle, parr, _cam_array(cams), len(cams), pa,
+                                        C.byref(o), C.byref(frame.handle), _stream(stream)))
+    frame.ctx = ctx
+    return images, frame
+
+
 def loss_grad(ctx, rendered, targets, cams, lam=0.2, *, want_grad=True, stream=None):
     """Loss (device scalar tensor) and per-view image gradients."""
     dev = rendered[0].device

@@ -249,6 +249,7 @@ static gs_status build_views(Frame& f, const gs_camera* cams, int nv, float* con
     d.tiles_x = (c.width + f.tile - 1) / f.tile;
     d.tiles_y = (c.height + f.tile - 1) / f.tile;
     d.tile_offset = (int)tiles;
+    d.entry_off = (uint32_t)((size_t)v * (size_t)f.n);  // multi-scene frames overwrite these
     d.pix_offset = pix;
     d.image = images != nullptr ? images[v] : nullptr;
     d.dimg = nullptr;
@@ -270,7 +271,7 @@ static gs_status build_views(Frame& f, const gs_camera* cams, int nv, float* con
 // Sizes the frame's buffers for its views; s: the stream of the calling pass.
 static gs_status frame_buffers(Frame& f, hipStream_t s) {
   Ctx* c = f.ctx;
-  const size_t vn = (size_t)f.views * (size_t)f.n;
+  const size_t vn = (size_t)f.entries;
   gs_status st;
   if (f.last_use == nullptr) {
     GS_HIP(hipEventCreateWithFlags(&f.last_use, hipEventDisableTiming));
@@ -294,7 +295,7 @@ static gs_status frame_buffers(Frame& f, hipStream_t s) {
   ENS(f.finalT, (size_t)f.total_pix * 4);
   ENS(f.ncon, (size_t)f.total_pix * 4);
   if (f.keep_radii) ENS(f.radii, vn * 4);
-  const size_t acc_bytes = (size_t)f.views * kAccStride * (size_t)f.n * 4;
+  const size_t acc_bytes = f.multi ? 0 : vn * kAccStride * 4;  // forward-only frames need none
   if (f.acc.cap < acc_bytes) {
     ENS(f.acc, acc_bytes);
     f.acc_zeroed = false;
@@ -597,6 +598,9 @@ gs_status gs_render_fwd(gs_ctx* ctx, gs_params params, const gs_camera* cams, in
   }
   Frame& f = *fr;
   f.n = params.n;
+  f.entries = (int64_t)n_views * params.n;
+  f.multi = false;
+  f.n_groups = 0;
   f.views = n_views;
   f.tile = tile;
   f.depth = depth;
@@ -613,8 +617,8 @@ gs_status gs_render_fwd(gs_ctx* ctx, gs_params params, const gs_camera* cams, in
     if (fresh) frame_delete(fr);
     return st;
   }
-  if (!f.acc_zeroed) {
-    st = launch_fill_u32(f.acc.p, 0u, (size_t)f.views * kAccStride * (size_t)f.n, s);
+  if (!f.acc_zeroed && !f.multi) {
+    st = launch_fill_u32(f.acc.p, 0u, (size_t)f.entries * kAccStride, s);
     if (st != GS_OK) {
       if (fresh) frame_delete(fr);
       return st;
@@ -623,6 +627,134 @@ gs_status gs_render_fwd(gs_ctx* ctx, gs_params params, const gs_camera* cams, in
   }
   *state = fr;
   st = forward_stages(ctx, f, params_dev(params), s, 0);
+  if (st != GS_OK) return st;
+  GS_HIP(hipEventRecord(f.last_use, s));
+  return GS_OK;
+}
+
+gs_status gs_render_fwd_multi(gs_ctx* ctx, const gs_params* params, const gs_camera* cams,
+                              int32_t n_views, float* const* images, const gs_render_opts* opts,
+                              gs_frame** state, void* stream) {
+  if (ctx == nullptr || params == nullptr || cams == nullptr || images == nullptr ||
+      state == nullptr) {
+    set_error("gs_render_fwd_multi: null argument");
+    return GS_ERR_INVALID;
+  }
+  if (n_views < 1 || n_views > kMaxViews) {
+    set_error("gs_render_fwd_multi: n_views %d not in [1, %d]", n_views, kMaxViews);
+    return GS_ERR_INVALID;
+  }
+  uint64_t total = 0;
+  for (int v = 0; v < n_views; ++v) {
+    if (!valid_params(params[v], "gs_render_fwd_multi")) return GS_ERR_INVALID;
+    if (!valid_camera(cams[v], v)) return GS_ERR_INVALID;
+    if (images[v] == nullptr) {
+      set_error("gs_render_fwd_multi: images[%d] is null", v);
+      return GS_ERR_INVALID;
+    }
+    total += (uint64_t)params[v].n;
+  }
+  if (total >= 0xffffffffULL) {
+    set_error("gs_render_fwd_multi: the views' Gaussian counts sum past 2^32 - 1");
+    return GS_ERR_CAPACITY;
+  }
+  int tile = 16, depth = 256, flags = 0;
+  float bg[3] = {0.f, 0.f, 0.f};
+  if (opts != nullptr) {
+    tile = opts->tile;
+    depth = opts->lds_depth == 0 ? 256 : opts->lds_depth;
+    flags = opts->flags;
+    for (int k = 0; k < 3; ++k) bg[k] = opts->bg[k];
+  }
+  if ((flags & ~(GS_RENDER_PERSISTENT | GS_RENDER_LONGEST_FIRST)) != 0) {
+    set_error("gs_render_fwd_multi: render flags 0x%x not supported here", flags);
+    return GS_ERR_INVALID;
+  }
+  if ((tile != 8 && tile != 16 && tile != 32) ||
+      (depth != 32 && depth != 64 && depth != 128 && depth != 256)) {
+    set_error("gs_render_fwd_multi: tile %d / lds_depth %d", tile, depth);
+    return GS_ERR_INVALID;
+  }
+  if (tile == 8 && depth > 64) depth = 64;
+  // views grouped by scene (scenes in order of first appearance, views in order)
+  int order[kMaxViews], gid[kMaxViews], ng = 0;
+  const gs_params* gp[kMaxViews];
+  for (int v = 0; v < n_views; ++v) {
+    int g = 0;
+    while (g < ng && !(gp[g]->means == params[v].means && gp[g]->n == params[v].n &&
+                       gp[g]->sh_degree == params[v].sh_degree && gp[g]->sh == params[v].sh))
+      ++g;
+    if (g == ng) gp[ng++] = &params[v];
+    gid[v] = g;
+  }
+  gs_camera oc[kMaxViews];
+  float* oi[kMaxViews];
+  int m = 0;
+  for (int g = 0; g < ng; ++g)
+    for (int v = 0; v < n_views; ++v)
+      if (gid[v] == g) {
+        order[m] = v;
+        oc[m] = cams[v];
+        oi[m] = images[v];
+        ++m;
+      }
+  gs_status st = set_device(ctx);
+  if (st != GS_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  gs_frame* fr = *state;
+  const bool fresh = (fr == nullptr);
+  if (fresh) {
+    fr = new (std::nothrow) gs_frame();
+    if (fr == nullptr) {
+      set_error("gs_render_fwd_multi: out of host memory");
+      return GS_ERR_NOMEM;
+    }
+    fr->ctx = ctx;
+    ctx_retain(ctx);
+  } else if (fr->ctx != ctx) {
+    set_error("gs_render_fwd_multi: frame belongs to another context");
+    return GS_ERR_INVALID;
+  }
+  Frame& f = *fr;
+  f.n = 0;
+  f.entries = (int64_t)total;
+  f.multi = true;
+  f.views = n_views;
+  f.tile = tile;
+  f.depth = depth;
+  f.persistent = (flags & GS_RENDER_PERSISTENT) != 0;
+  f.lpt = f.persistent && (flags & GS_RENDER_LONGEST_FIRST) != 0;
+  f.tile_order = nullptr;
+  f.sh_degree = -1;
+  f.K = 0;
+  f.keep_radii = false;
+  f.screen_kept = false;
+  st = build_views(f, oc, n_views, oi, bg);
+  if (st == GS_OK) {
+    uint32_t base = 0;
+    int v = 0;
+    f.n_groups = ng;
+    for (int g = 0; g < ng; ++g) {
+      SceneGroup& sg = f.groups[g];
+      sg.pd = params_dev(*gp[g]);
+      sg.v0 = v;
+      sg.nv = 0;
+      sg.base = base;
+      while (v < n_views && gid[order[v]] == g) {
+        f.vt.v[v].entry_off = base;
+        base += (uint32_t)gp[g]->n;
+        ++sg.nv;
+        ++v;
+      }
+    }
+    st = frame_buffers(f, s);
+  }
+  if (st != GS_OK) {
+    if (fresh) frame_delete(fr);
+    return st;
+  }
+  *state = fr;
+  st = forward_stages(ctx, f, f.groups[0].pd, s, 0);
   if (st != GS_OK) return st;
   GS_HIP(hipEventRecord(f.last_use, s));
   return GS_OK;
@@ -638,12 +770,23 @@ namespace isogs {
 // overflow word set when the records do not fit), as a captured graph needs.
 gs_status forward_stages(Ctx* ctx, Frame& f, const ParamsDev& pd, hipStream_t s, uint32_t cap) {
   gs_status st = GS_OK;
-  const uint32_t vn = (uint32_t)((size_t)f.views * (size_t)f.n);
+  const uint32_t vn = (uint32_t)f.entries;
 
-  // 1. projection + SH
+  // 1. projection + SH (a multi-scene frame: one launch per scene, each on its
+  // views' entry range)
   {
     StageTimer tm(ctx, ST_PROJECT, s);
-    st = launch_preprocess_fwd(pd, f.vt, f, s);
+    if (!f.multi) {
+      st = launch_preprocess_fwd(pd, f.vt, f, s);
+    } else {
+      for (int g = 0; g < f.n_groups && st == GS_OK; ++g) {
+        const SceneGroup& sg = f.groups[g];
+        ViewTable vg = f.vt;
+        vg.n = sg.nv;
+        for (int k = 0; k < sg.nv; ++k) vg.v[k] = f.vt.v[sg.v0 + k];
+        st = launch_preprocess_fwd(sg.pd, vg, f, s, sg.base);
+      }
+    }
   }
   if (st != GS_OK) return st;
   // 2. (view, Gaussian) entries in (depth bits, index) order
@@ -878,6 +1021,10 @@ gs_status gs_render_bwd(gs_ctx* ctx, gs_frame* frame, gs_params params,
     return GS_ERR_INVALID;
   }
   Frame& f = *frame;
+  if (f.multi) {
+    set_error("gs_render_bwd: the frame holds views of several scenes (forward only)");
+    return GS_ERR_UNSUPPORTED;
+  }
   if (!f.acc_zeroed) {
     set_error("gs_render_bwd: the frame's screen-space sums were kept by the previous backward; "
               "run a forward first");
@@ -920,6 +1067,10 @@ gs_status gs_density_accumulate(gs_ctx* ctx, gs_frame* frame, gs_density_stats s
     return GS_ERR_INVALID;
   }
   Frame& f = *frame;
+  if (f.multi) {
+    set_error("gs_density_accumulate: the frame holds views of several scenes");
+    return GS_ERR_UNSUPPORTED;
+  }
   if (stats.n != f.n) {
     set_error("gs_density_accumulate: statistics hold %lld entries, the frame %lld",
               (long long)stats.n, (long long)f.n);
@@ -1183,6 +1334,12 @@ gs_status gs_frame_export(gs_frame* frame, int32_t what, int32_t view, void* dst
   if (view < -1 || view >= f.views) {
     set_error("gs_frame_export: view %d out of range", view);
     return GS_ERR_INVALID;
+  }
+  if (f.multi && what != GS_EXPORT_KEYS && what != GS_EXPORT_VALUES && what != GS_EXPORT_RANGES &&
+      what != GS_EXPORT_FINAL_T && what != GS_EXPORT_N_CONTRIB) {
+    set_error("gs_frame_export: per-(view, Gaussian) arrays of a multi-scene frame are not "
+              "exported");
+    return GS_ERR_UNSUPPORTED;
   }
   gs_status st = set_device(f.ctx);
   if (st != GS_OK) return st;

@@ -104,7 +104,7 @@ gs_status reserve_and_capture(gs_graph* g) {
     if (st == GS_OK) st = buf_ensure(ctx, f.tval[k], ((size_t)g->cap + 1) * 4, cs, f.last_use);
     if (st != GS_OK) return st;
   }
-  const uint32_t vn = (uint32_t)((size_t)f.views * (size_t)f.n);
+  const uint32_t vn = (uint32_t)f.entries;
   const uint32_t most = std::max(std::max(g->cap, vn), (uint32_t)f.vt.total_tiles);
   gs_status st = sort_reserve(ctx, f.ss, most, cs);
   if (st == GS_OK) st = loss_reserve(ctx, g->loss, g->W, g->H, g->nv, cs);

@@ -57,7 +57,7 @@ struct CamDev {
   float campos[3];
   int W, H, tiles_x, tiles_y;
   int tile_offset;  // first global tile id of the view
-  int reserved;
+  uint32_t entry_off;  // first (view, Gaussian) entry of the view (view * n unless multi-scene)
   long long pix_offset;  // first pixel of the view in the frame-wide pixel arrays
   float* image;          // forward output [3][H][W]
   const float* dimg;     // upstream gradient [3][H][W]
@@ -92,6 +92,13 @@ struct GradsDev {
   int accumulate;
   int keep_screen;  // leave the screen-space accumulators for export (no clearing)
 };
+
+__host__ __device__ inline int view_of_entry(const ViewTable& vt, uint32_t e) {
+  int v = 0;
+  for (int i = 1; i < vt.n; ++i)
+    if (e >= vt.v[i].entry_off) v = i;
+  return v;
+}
 
 __host__ __device__ inline int view_of_tile(const ViewTable& vt, int gt) {
   int v = 0;
@@ -210,9 +217,21 @@ struct SortScratch {
   hipEvent_t prior = nullptr;  // last use of the owning frame (see buf_ensure)
 };
 
+// Views of one scene inside a multi-scene frame: views [v0, v0 + nv) of the
+// frame's table, entries [base, base + nv * pd.n).
+struct SceneGroup {
+  ParamsDev pd;
+  int v0 = 0, nv = 0;
+  uint32_t base = 0;
+};
+
 struct Frame {
   Ctx* ctx = nullptr;
-  int64_t n = 0;
+  int64_t n = 0;        // Gaussians per view (0 in a multi-scene frame)
+  int64_t entries = 0;  // (view, Gaussian) entries: views * n, or the sum over the views
+  bool multi = false;   // views of several scenes (forward only)
+  SceneGroup groups[kMaxViews];
+  int n_groups = 0;
   int views = 0;
   int tile = 16;
   int depth = 256;
@@ -274,8 +293,10 @@ gs_status backward_stages(Ctx* ctx, Frame& f, const ParamsDev& pd, const GradsDe
 
 // ----------------------------------------------------------- kernel hosts
 // preprocess.hip
+// Projection of views vt (entries laid out [v][p.n] from entry `base` of the frame's
+// per-entry arrays).
 gs_status launch_preprocess_fwd(const ParamsDev& p, const ViewTable& vt, Frame& f,
-                                hipStream_t s);
+                                hipStream_t s, size_t base = 0);
 gs_status launch_preprocess_bwd(const ParamsDev& p, const ViewTable& vt, Frame& f,
                                 const GradsDev& g, hipStream_t s);
 gs_status launch_init_points(const float* xyz, int64_t n, const gs_init_opts& o,

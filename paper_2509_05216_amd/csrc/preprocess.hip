@@ -753,13 +753,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
 }  // namespace
 
 gs_status launch_preprocess_fwd(const ParamsDev& p, const ViewTable& vt, Frame& f,
-                                hipStream_t s) {
+                                hipStream_t s, size_t base) {
   const int blocks = (int)((p.n + 255) / 256);
-  auto* sp = (float4*)f.splat.p;
-  auto* rc = (uint2*)f.rect.p;
-  auto* dk = (uint32_t*)f.dkey.p;
-  auto* cm = (uint8_t*)f.clampm.p;
-  auto* rd = f.keep_radii ? (int32_t*)f.radii.p : nullptr;
+  auto* sp = (float4*)f.splat.p + 3 * base;
+  auto* rc = (uint2*)f.rect.p + base;
+  auto* dk = (uint32_t*)f.dkey.p + base;
+  auto* cm = (uint8_t*)f.clampm.p + base;
+  auto* rd = f.keep_radii ? (int32_t*)f.radii.p + base : nullptr;
   switch (p.sh_degree) {
     case 0: hipLaunchKernelGGL(k_preprocess_fwd<0>, dim3(blocks), dim3(256), 0, s, p, vt, sp, rc, dk, cm, rd); break;
     case 1: hipLaunchKernelGGL(k_preprocess_fwd<1>, dim3(blocks), dim3(256), 0, s, p, vt, sp, rc, dk, cm, rd); break;

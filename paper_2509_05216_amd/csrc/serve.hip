@@ -4,13 +4,14 @@
 // Scenes stay on the device (caller-owned parameters).  Requests (scene,
 // camera, output image) are queued as they arrive.  Each of n_slots worker
 // threads owns a HIP stream and a frame; whenever it is free it takes the
-// scene of the oldest pending request and up to max_batch_views pending
-// requests of that scene — of any resolutions — and renders them as one
-// multi-view forward (one projection, one sort, one compositing launch).
+// oldest pending requests, up to max_batch_views of them, of any scenes and
+// resolutions, and renders them as one multi-scene forward (one projection
+// launch per scene in the batch, one depth sort, one tile sort, one
+// compositing launch over all their tiles).
 // Before a batch starts, its device scratch is estimated and admitted against
 // the server's memory budget together with the scratch the other slots hold;
 // a batch that does not fit waits until a running batch completes.  Batches
-// of different scenes run concurrently on different streams, so requests
+// run concurrently on different streams, so requests
 // arriving while others are on the device are admitted as soon as a slot and
 // memory free up.  A request's latency runs from submission to the completion
 // of its batch on the device.  The rendered image of a request does not
@@ -80,14 +81,14 @@ struct gs_server {
 
 namespace {
 
-// Scratch a forward of these views over n Gaussians is expected to need.
-size_t estimate_bytes(int64_t n, const std::vector<Request>& b) {
+// Scratch a forward of these views is expected to need (vn: the sum over the
+// views of their scenes' Gaussian counts).
+size_t estimate_bytes(size_t vn, const std::vector<Request>& b) {
   size_t pix = 0;
   for (const Request& r : b) pix += (size_t)r.cam.width * r.cam.height;
-  const size_t vn = (size_t)n * b.size();
-  // per (view, Gaussian): splat 48, rect 8, keys/indices 20, clamp 1, scan 4, accum 48;
+  // per (view, Gaussian): splat 48, rect 8, keys/indices 20, clamp 1, scan 4;
   // records: about 4 per visible Gaussian, 16 bytes each; per pixel: T and count
-  return vn * 129 + vn * 4 * 16 + pix * 8 + ((size_t)64 << 20);
+  return vn * 81 + vn * 4 * 16 + pix * 8 + ((size_t)64 << 20);
 }
 
 void worker_main(gs_server* sv, int slot_id) {
@@ -95,20 +96,21 @@ void worker_main(gs_server* sv, int slot_id) {
   (void)hipSetDevice(sv->ctx->device);
   for (;;) {
     std::vector<Request> batch;
-    gs_params scene_params;  // copied under the lock: add_scene may grow the vector
+    gs_params view_params[kMaxViews];  // copied under the lock: add_scene may grow the vector
     size_t need = 0;
     {
       std::unique_lock<std::mutex> lk(sv->mu);
       for (;;) {
         if (sv->stop) return;
         if (!sv->pending.empty()) {
-          const int scene = sv->pending.front().scene;
           std::vector<Request> cand;
+          size_t vn = 0;
           for (const Request& r : sv->pending) {
-            if (r.scene == scene) cand.push_back(r);
+            cand.push_back(r);
+            vn += (size_t)sv->scenes[r.scene].n;
             if ((int)cand.size() >= sv->opts.max_batch_views) break;
           }
-          need = estimate_bytes(sv->scenes[scene].n, cand);
+          need = estimate_bytes(vn, cand);
           const size_t held = std::max(slot.bytes, slot.reserved);
           const size_t others = sv->ledger - held;
           const bool fits = sv->opts.mem_budget == 0 ||
@@ -121,7 +123,7 @@ void worker_main(gs_server* sv, int slot_id) {
               sv->pending.erase(it);
             }
             batch = std::move(cand);
-            scene_params = sv->scenes[scene];
+            for (size_t i = 0; i < batch.size(); ++i) view_params[i] = sv->scenes[batch[i].scene];
             slot.reserved = std::max(need, slot.bytes);
             sv->ledger = sv->ledger - held + slot.reserved;
             sv->peak_ledger = std::max(sv->peak_ledger, sv->ledger);
@@ -142,8 +144,8 @@ void worker_main(gs_server* sv, int slot_id) {
       cams[i] = batch[i].cam;
       images[i] = batch[i].out;
     }
-    gs_status st = gs_render_fwd(sv->ctx, scene_params, cams, (int32_t)batch.size(), images,
-                                 &sv->opts.render, &slot.frame, slot.stream);
+    gs_status st = gs_render_fwd_multi(sv->ctx, view_params, cams, (int32_t)batch.size(), images,
+                                       &sv->opts.render, &slot.frame, slot.stream);
     if (st == GS_OK && hipStreamSynchronize(slot.stream) != hipSuccess)
       st = hip_fail(hipErrorUnknown, "server batch");
     const Clock::time_point done = Clock::now();

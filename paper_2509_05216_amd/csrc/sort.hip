@@ -329,7 +329,7 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(
 // each pass stores 64 consecutive records and no lane idles behind a large
 // rectangle.  An entry whose records would pass the capacity writes none and
 // sets the overflow word.
-__global__ __launch_bounds__(256) void k_emit(ViewTable vt, int n_gauss,
+__global__ __launch_bounds__(256) void k_emit(ViewTable vt,
                                               const uint32_t* __restrict__ sidx,
                                               const uint32_t* __restrict__ srx,
                                               const uint32_t* __restrict__ sry,
@@ -346,7 +346,7 @@ __global__ __launch_bounds__(256) void k_emit(ViewTable vt, int n_gauss,
     const int x0 = (int)(r.x & 0xffffu), y0 = (int)(r.x >> 16);
     const int x1 = (int)(r.y & 0xffffu), y1 = (int)(r.y >> 16);
     if (x1 >= x0 && y1 >= y0) {
-      const int v = (int)(idx / (uint32_t)n_gauss);
+      const int v = view_of_entry(vt, idx);
       tx = (uint32_t)vt.v[v].tiles_x;
       o = offs[i];
       const uint32_t nd = (uint32_t)((x1 - x0 + 1) * (y1 - y0 + 1));
@@ -567,7 +567,7 @@ gs_status launch_emit(const ViewTable& vt, Frame& f, const uint32_t* sidx, const
   if (count == 0) return GS_OK;
   const size_t cap_bytes = f.tkey[0].cap < f.tval[0].cap ? f.tkey[0].cap : f.tval[0].cap;
   const uint32_t cap = (uint32_t)(cap_bytes / sizeof(uint32_t));
-  hipLaunchKernelGGL(k_emit, dim3((count + 255) / 256), dim3(256), 0, s, vt, (int)f.n, sidx, srx,
+  hipLaunchKernelGGL(k_emit, dim3((count + 255) / 256), dim3(256), 0, s, vt, sidx, srx,
                      sry, (const uint32_t*)f.offs.p, count, cap, (uint32_t*)f.tkey[0].p,
                      (uint32_t*)f.tval[0].p, overflow);
   GS_LAUNCHED("emit");

@@ -111,3 +111,51 @@ def test_invalid_requests_are_rejected(P, ctx, scenes):
     with pytest.raises(P.IsogsError):
         srv.wait(t)                      # already collected
     srv.close()
+
+
+def test_multi_scene_forward_matches_single_scene_and_oracle(P, ctx, scenes):
+    """Views of two scenes (interleaved, mixed sizes) in one forward: every view
+    bit-identical to rendering it alone, and within the image bar of the oracle;
+    the persistent longest-first form gives the same images."""
+    raw, params = scenes
+    reqs = _requests(P, n=7, seed=5)
+    sids = [sid for sid, _, _ in reqs]
+    assert len(set(sids)) == 2
+    cams = [cam for _, _, cam in reqs]
+    outs = {}
+    for flags in (0, P.PERSISTENT | P.LONGEST_FIRST):
+        imgs, fr = P.render_fwd_multi(ctx, [params[s] for s in sids], cams, flags=flags)
+        torch.cuda.synchronize()
+        outs[flags] = [i.clone() for i in imgs]
+        with pytest.raises(P.IsogsError):          # forward only
+            P.render_bwd(ctx, fr, params[0], [torch.zeros_like(i) for i in imgs])
+        with pytest.raises(P.IsogsError):
+            fr.export("screen_grads")
+        fr.release()
+    for k, (sid, d, cam) in enumerate(reqs):
+        alone, fr = P.render_fwd(ctx, params[sid], [cam])
+        torch.cuda.synchronize()
+        assert torch.equal(outs[0][k], alone[0])
+        assert torch.equal(outs[P.PERSISTENT | P.LONGEST_FIRST][k], alone[0])
+        fr.release()
+        if k < 3:
+            assert_image(pipeline.forward_view(raw[sid].params, d, 16), outs[0][k].cpu().numpy())
+
+
+def test_server_batches_across_scenes(P, ctx, scenes):
+    """Requests of different scenes submitted together land in shared batches."""
+    _, params = scenes
+    reqs = _requests(P, n=12, seed=6)
+    srv = P.Server(ctx, n_slots=1, max_batch_views=6)
+    ids = [srv.add_scene(p) for p in params]
+    tickets = [srv.submit(ids[sid], cam) for sid, _, cam in reqs]
+    srv.drain()
+    torch.cuda.synchronize()
+    st = srv.stats()
+    assert st["completed"] == 12 and st["mean_batch_views"] > 1.0
+    for (sid, _, cam), (t, out) in zip(reqs, tickets):
+        imgs, fr = P.render_fwd(ctx, params[sid], [cam])
+        torch.cuda.synchronize()
+        assert torch.equal(out, imgs[0])
+        fr.release()
+    srv.close()

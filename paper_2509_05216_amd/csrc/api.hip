@@ -149,7 +149,7 @@ size_t Frame::bytes() const {
              sidx[1].cap + clampm.cap + offs.cap + tkey[0].cap + tkey[1].cap + tval[0].cap +
              tval[1].cap + ranges.cap + finalT.cap + ncon.cap + acc.cap + ss.hist.cap +
              ss.partial.cap + ss.total.cap + words.cap + okey[0].cap + okey[1].cap +
-             oval[0].cap + oval[1].cap + radii.cap;
+             oval[0].cap + oval[1].cap + radii.cap + gmu.cap;
   return s;
 }
 
@@ -160,12 +160,17 @@ static void frame_free(Frame* f) {
                    &f->tkey[1], &f->tval[0], &f->tval[1], &f->ranges,     &f->finalT,
                    &f->ncon,    &f->acc,     &f->ss.hist, &f->ss.partial, &f->ss.total,
                    &f->words,   &f->okey[0], &f->okey[1], &f->oval[0],    &f->oval[1],
-                   &f->radii};
+                   &f->radii,   &f->gmu};
   for (DevBuf* b : all) buf_free(c, *b);
   if (f->pinned != nullptr) (void)hipHostFree(f->pinned);
   f->pinned = nullptr;
   if (f->last_use != nullptr) (void)hipEventDestroy(f->last_use);
   f->last_use = nullptr;
+  if (f->side != nullptr) (void)hipStreamDestroy(f->side);
+  if (f->fork_ev != nullptr) (void)hipEventDestroy(f->fork_ev);
+  if (f->join_ev != nullptr) (void)hipEventDestroy(f->join_ev);
+  f->side = nullptr;
+  f->fork_ev = f->join_ev = nullptr;
   f->ss.prior = nullptr;
 }
 
@@ -295,6 +300,14 @@ static gs_status frame_buffers(Frame& f, hipStream_t s) {
   ENS(f.finalT, (size_t)f.total_pix * 4);
   ENS(f.ncon, (size_t)f.total_pix * 4);
   if (f.keep_radii) ENS(f.radii, vn * 4);
+  if (!f.multi && f.views > 1) {
+    ENS(f.gmu, (size_t)f.n * 12);
+    if (f.side == nullptr) {
+      GS_HIP(hipStreamCreateWithFlags(&f.side, hipStreamNonBlocking));
+      GS_HIP(hipEventCreateWithFlags(&f.fork_ev, hipEventDisableTiming));
+      GS_HIP(hipEventCreateWithFlags(&f.join_ev, hipEventDisableTiming));
+    }
+  }
   const size_t acc_bytes = f.multi ? 0 : vn * kAccStride * 4;  // forward-only frames need none
   if (f.acc.cap < acc_bytes) {
     ENS(f.acc, acc_bytes);

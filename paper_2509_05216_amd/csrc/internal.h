@@ -244,6 +244,11 @@ struct Frame {
   DevBuf splat, rect, dkey, dkw[2], sidx[2], clampm, offs, tkey[2], tval[2], ranges, finalT,
       ncon, acc;
   DevBuf radii;               // int32[views][n] pixel radii (GS_RENDER_RADII)
+  DevBuf gmu;                 // float[3][n]: the colour kernel's mean-gradient term (several views)
+  // the projection backward's geometry kernel runs on `side` beside the colour
+  // kernel on the call's stream (fork / join by the two events)
+  hipStream_t side = nullptr;
+  hipEvent_t fork_ev = nullptr, join_ev = nullptr;
   bool keep_radii = false;    // this forward writes radii
   bool screen_kept = false;   // the last backward kept its screen-space sums
   int tkey_sel = 0;  // which of tkey/tval holds the sorted records

@@ -657,8 +657,9 @@ __device__ inline void sh_grad_w(float x, float y, float z, int deg, const float
   gy = fmaf(6.f * xy, t, gy);
 }
 
-// Colour part; runs after k_preprocess_bwd_geom (it adds to the mean gradient
-// that kernel wrote) and clears every accumulator it finds non-zero.  All of
+// Colour part; runs beside k_preprocess_bwd_geom (on another stream), writes its
+// term of the mean gradient to gmu (added to the geometry kernel's by
+// k_add_means once both are done) and clears every accumulator it finds non-zero.  All of
 // the Gaussian's coefficients and their gradient sums stay in registers while
 // the views are walked one at a time, so each view's basis is evaluated once,
 // and its direction gradient is one weighted basis gradient: the weight of
@@ -667,7 +668,7 @@ __device__ inline void sh_grad_w(float x, float y, float z, int deg, const float
 template <int DEG>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_preprocess_bwd_sh(
     ParamsDev prm, ViewTable vt, float* __restrict__ accC, const uint8_t* __restrict__ clampm,
-    GradsDev gout) {
+    GradsDev gout, float* __restrict__ gmu) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int n = prm.n;
   if (i >= n) return;
@@ -732,9 +733,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     gmf[1] += (gy - y * dot) * inv;
     gmf[2] += (gz - z * dot) * inv;
   }
-  if (any_col) {
 #pragma unroll
-    for (int k = 0; k < 3; ++k) gout.means[(size_t)k * n + i] += gmf[k];
+  for (int k = 0; k < 3; ++k) gmu[(size_t)k * n + i] = gmf[k];  // zero without colour gradient
+  if (any_col) {
 #pragma unroll
     for (int j = 0; j < nb; ++j)
 #pragma unroll
@@ -748,6 +749,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
   } else if (!add) {
     for (int j = 0; j < nb * 3; ++j) gout.sh[(size_t)j * n + i] = 0.f;
   }
+}
+
+// means gradient += the colour kernel's term (after both backward kernels)
+__global__ __launch_bounds__(256) void k_add_means(float* __restrict__ means,
+                                                   const float* __restrict__ gmu, int n3) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n3) means[i] += gmu[i];
 }
 
 }  // namespace
@@ -789,11 +797,20 @@ gs_status launch_preprocess_bwd(const ParamsDev& p, const ViewTable& vt, Frame& 
     GS_LAUNCHED("preprocess_bwd_one");
     return GS_OK;
   }
-  auto go = [&](auto kern) {
-    hipLaunchKernelGGL(kern, dim3(blocks), dim3(256), 0, s, p, vt, accC, cm, g);
-  };
-  hipLaunchKernelGGL(k_preprocess_bwd_geom, dim3(blocks), dim3(256), 0, s, p, vt, accG, g);
+  // the geometry kernel (instruction-bound) on the frame's side stream, the colour
+  // kernel (memory-bound) on s, joined before the colour kernel's mean term is added
+  float* gmu = (float*)f.gmu.p;
+  if (gmu == nullptr || f.side == nullptr) {
+    set_error("internal: the frame has no side stream / mean scratch for %d views", vt.n);
+    return GS_ERR_INVALID;
+  }
+  GS_HIP(hipEventRecord(f.fork_ev, s));
+  GS_HIP(hipStreamWaitEvent(f.side, f.fork_ev, 0));
+  hipLaunchKernelGGL(k_preprocess_bwd_geom, dim3(blocks), dim3(256), 0, f.side, p, vt, accG, g);
   GS_LAUNCHED("preprocess_bwd_geom");
+  auto go = [&](auto kern) {
+    hipLaunchKernelGGL(kern, dim3(blocks), dim3(256), 0, s, p, vt, accC, cm, g, gmu);
+  };
   switch (p.sh_degree) {
     case 0: go(k_preprocess_bwd_sh<0>); break;
     case 1: go(k_preprocess_bwd_sh<1>); break;
@@ -801,6 +818,11 @@ gs_status launch_preprocess_bwd(const ParamsDev& p, const ViewTable& vt, Frame& 
     default: go(k_preprocess_bwd_sh<3>); break;
   }
   GS_LAUNCHED("preprocess_bwd_sh");
+  GS_HIP(hipEventRecord(f.join_ev, f.side));
+  GS_HIP(hipStreamWaitEvent(s, f.join_ev, 0));
+  const int n3 = 3 * p.n;
+  hipLaunchKernelGGL(k_add_means, dim3((n3 + 255) / 256), dim3(256), 0, s, g.means, gmu, n3);
+  GS_LAUNCHED("add_means");
   return GS_OK;
 }
 

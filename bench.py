@@ -80,6 +80,8 @@ def parse():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-train", action="store_true", help="skip the 1M-Gaussian training run")
     ap.add_argument("--no-c3", action="store_true", help="skip the in-situ 18M-Gaussian 4096^2 step")
+    ap.add_argument("--cpu-c1", action="store_true",
+                    help="also run the oracle over one whole 1024^2 view of the 1M scene (minutes)")
     ap.add_argument("--train-iters", type=int, default=500)
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--workload", choices=["kingsnake4m", "miranda18m"], default="kingsnake4m",
@@ -576,7 +578,21 @@ def cpu_c0_full(cores):
             "sample": "full run: 10k Gaussians, 8 views of 256^2, fwd + L1/SSIM + bwd"}
 
 
-def cpu_baseline(scene, cam_d, target, tile_frac=1 / 64, tile=16):
+def cpu_c1_view(cores):
+    """The oracle's fwd + loss + bwd of one whole 1024^2 view of the 1M-Gaussian scene on
+    the host's cores (every tile; no sampling)."""
+    import gsscenes
+    from oracle import camera as ocam
+    scene = gsscenes.make_scene("iso1m")
+    cam = ocam.to_float32(ocam.orbit_cameras(128, 2.5, 60.0, 1024, 1024)[0])
+    target = make_targets(scene, [cam], coarse=128)[0]
+    r = cpu_baseline(scene, cam, target, tile_frac=1.0, with_c0=False)
+    return {"mpix_per_s": r["value"], "seconds": r["seconds"], "stages_s": r["stages_s"],
+            "cores": r["cores"],
+            "sample": "full run: 1M Gaussians (SH3), one 1024^2 view, every tile, fwd + L1/SSIM + bwd"}
+
+
+def cpu_baseline(scene, cam_d, target, tile_frac=1 / 64, tile=16, with_c0=True):
     """The oracle's fwd+bwd on one 2048^2 view of the 4M scene on the host's cores:
     projection and parameter backward on all Gaussians (threads over chunks),
     binning + compositing fwd/bwd on a seeded 1/64 of the tiles (processes), scaled
@@ -599,6 +615,7 @@ def cpu_baseline(scene, cam_d, target, tile_frac=1 / 64, tile=16):
                          n, cores)
         pr = _merge(parts)
         t_proj = time.perf_counter() - t0
+        log(f"oracle projection of {n} Gaussians: {t_proj:.1f}s on {cores} threads")
         rng = np.random.default_rng(1234)
         n_tiles = max(1, int(round(tx * ty * tile_frac)))
         sample = rng.choice(tx * ty, size=n_tiles, replace=False)
@@ -615,6 +632,7 @@ def cpu_baseline(scene, cam_d, target, tile_frac=1 / 64, tile=16):
         with mp.get_context("fork").Pool(cores) as pool:
             accs = pool.map(_tile_worker, [list(c) for c in np.array_split(sample, cores)])
         t_tiles = time.perf_counter() - t0
+        log(f"oracle compositing fwd/bwd of {n_tiles} tiles: {t_tiles:.1f}s on {cores} processes")
         _CPU.clear()
         acc = {k: sum(a[k] for a in accs) for k in accs[0]}
         share = lens[sample].sum() / max(lens.sum(), 1)
@@ -633,7 +651,7 @@ def cpu_baseline(scene, cam_d, target, tile_frac=1 / 64, tile=16):
         t_loss = time.perf_counter() - t0
         _CPU.clear()
     total = t_proj + t_pbwd + t_tiles / max(share, 1e-12) + t_loss
-    c0 = cpu_c0_full(cores)
+    c0 = cpu_c0_full(cores) if with_c0 else None
     return {"value": round(W * H / total / 1e6, 6), "unit": "Mpix/s", "cores": cores,
             "kind": "oracle",
             "sample": (f"one {W}x{H} view of the {n}-Gaussian scene, float64 numpy on {cores} "
@@ -858,6 +876,8 @@ def main():
     if not args.no_cpu_baseline:
         t0 = time.perf_counter()
         out["cpu_baseline"] = cpu_baseline(scene, cams_d[0], targets_np[0], tile=args.tile)
+        if args.cpu_c1:
+            out["cpu_baseline"]["c1_full_view"] = cpu_c1_view(_cpu_cores())
         log(f"cpu baseline in {time.perf_counter() - t0:.1f}s")
     print(json.dumps(out), flush=True)
 

@@ -22,8 +22,8 @@
 // the opacity divides the sixth once per (tile, Gaussian) when the sums are
 // flushed).  They are
 // reduce-scattered across the wave (eight by two gfx950 permlane swaps and DPP
-// steps inside 16-lane rows, the ninth by DPP row sums: about 23 VALU
-// instructions for all nine), added
+// steps inside 16-lane rows, the ninth by DPP row sums: 21 VALU instructions
+// for all nine), added
 // across the workgroup's waves with LDS float atomics and to the per-Gaussian
 // accumulators with one global atomic per component per (tile, Gaussian).
 //
@@ -241,6 +241,7 @@ __device__ inline void fwd_tile(Stage<TILE * TILE, DEPTH>& st, const ViewTable& 
       const float alpha = fminf(kAlphaMax, s.q0.w * __builtin_amdgcn_exp2f(p2));
       uint64_t m_use = ~done_m & __builtin_amdgcn_ballot_w64(!(p2 > 0.f)) &
                        __builtin_amdgcn_ballot_w64(!(alpha < kAlphaMin));
+      if (m_use == 0) return;  // no lane takes this splat: nothing changes
       // weight alpha T and the transmittance after, T - alpha T = T (1 - alpha)
       const float wa = alpha * T;
       const float Tn = T - wa;
@@ -369,16 +370,6 @@ __global__ __launch_bounds__(TILE* TILE) void k_blend_fwd_persistent(
 }
 
 // ---------------------------------------------------------------- reduction
-__device__ inline float dpp_f(float x, int ctrl) {
-  // row_mask / bank_mask all lanes, bound_ctrl off: every source lane is valid here
-  switch (ctrl) {
-    case 0xB1: return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0xB1, 0xF, 0xF, false));
-    case 0x4E: return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x4E, 0xF, 0xF, false));
-    case 0x141: return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x141, 0xF, 0xF, false));
-    default: return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x128, 0xF, 0xF, false));
-  }
-}
-
 // (a + partner) where lanes 0-31 pair with 32-63: lower lanes get a's sum,
 // upper lanes b's sum.
 __device__ inline float swap32_sum(float a, float b) {
@@ -410,27 +401,41 @@ __device__ inline int lane_slot(int lane) {
 }
 
 // Adds the wave sums of g[0..8] to the sum table (LDS atomics): the lane that
-// owns sum k (slot = lane_slot(lane) = k) adds it at dst, its address for k;
-// hi8: bit 3 of the lane index.
-__device__ inline void wave_reduce_add(const float* g, float* dst, int slot, bool hi8) {
+// owns sum k (slot = lane_slot(lane) = k) adds it at dst, its address for k.
+__device__ inline void wave_reduce_add(const float* g, float* dst, int slot) {
   const float a0 = swap32_sum(g[0], g[4]);
   const float a1 = swap32_sum(g[1], g[5]);
   const float a2 = swap32_sum(g[2], g[6]);
   const float a3 = swap32_sum(g[3], g[7]);
   const float b0 = swap16_sum(a0, a1);
   const float b1 = swap16_sum(a2, a3);
-  // xor 8: lanes 0-7 keep b0 and take the partner's b0, lanes 8-15 likewise b1
-  const float k = hi8 ? b1 : b0, sx = hi8 ? b0 : b1;
-  float d = k + dpp_f(sx, 0x128);
-  d += dpp_f(d, 0x141);  // row_half_mirror
-  d += dpp_f(d, 0x4E);   // quad_perm [2,3,0,1]
-  d += dpp_f(d, 0xB1);   // quad_perm [1,0,3,2]
-  float e = g[8] + dpp_f(g[8], 0x128);
-  e += dpp_f(e, 0x141);
-  e += dpp_f(e, 0x4E);
-  e += dpp_f(e, 0xB1);
-  const float v = slot == 8 ? e : d;
-  if (slot >= 0 && v != 0.f) atomicAdd(dst, v);
+  // xor 8 (row_ror:8): lanes 0-7 sum b0 with their partner's, lanes 8-15 b1 (two
+  // adds, each writing two of a row's four 4-lane banks); then the half mirror and
+  // two quad steps sum each 8-lane half.  The ninth value takes the same four steps
+  // on its own register, and its last step writes the row total into d's lanes
+  // 12-15, where lane 15 owns it.  A VALU write read by a DPP operand needs two
+  // wait states, which the interleaving and the s_nops provide (the compiler does
+  // not see inside the block, so the first s_nop covers the inputs' last writes).
+  float d, e;
+  asm("s_nop 1\n\t"
+      "v_add_f32_dpp %0, %2, %2 row_ror:8 row_mask:0xf bank_mask:0xc\n\t"
+      "v_add_f32_dpp %0, %3, %3 row_ror:8 row_mask:0xf bank_mask:0x3\n\t"
+      "v_add_f32_dpp %1, %4, %4 row_ror:8 row_mask:0xf bank_mask:0xf\n\t"
+      "s_nop 0\n\t"
+      "v_add_f32_dpp %0, %0, %0 row_half_mirror row_mask:0xf bank_mask:0xf\n\t"
+      "v_add_f32_dpp %1, %1, %1 row_half_mirror row_mask:0xf bank_mask:0xf\n\t"
+      "s_nop 0\n\t"
+      "v_add_f32_dpp %0, %0, %0 quad_perm:[2,3,0,1] row_mask:0xf bank_mask:0xf\n\t"
+      "v_add_f32_dpp %1, %1, %1 quad_perm:[2,3,0,1] row_mask:0xf bank_mask:0xf\n\t"
+      "s_nop 0\n\t"
+      "v_add_f32_dpp %0, %0, %0 quad_perm:[1,0,3,2] row_mask:0xf bank_mask:0xf\n\t"
+      "s_nop 0\n\t"
+      "v_add_f32_dpp %0, %1, %1 quad_perm:[1,0,3,2] row_mask:0xf bank_mask:0x8"
+      : "=&v"(d), "=&v"(e)
+      : "v"(b1), "v"(b0), "v"(g[8]));
+  (void)e;
+  // an LDS add of a zero sum is harmless, so no test guards it
+  if (slot >= 0) atomicAdd(dst, d);
 }
 
 template <int TILE, int DEPTH>
@@ -481,7 +486,6 @@ __device__ inline void bwd_tile(BwdSmem<TILE, DEPTH>& sm, const ViewTable& vt, i
   // (it starts as T_final * bg); dL/dalpha needs S only through this product
   float D = T * (dr * vt.bg[0] + dg * vt.bg[1] + db * vt.bg[2]);
   const int slot = lane_slot(lane);
-  const bool hi8 = (lane & 8) != 0;
   constexpr int kPart = BwdSmem<TILE, DEPTH>::kPart;
   // this lane's sum row (slot >= 0); the slot's column is added per pair
   float* const part_lane = part + (slot >= 0 ? slot : 0) * kPart;
@@ -537,25 +541,27 @@ __device__ inline void bwd_tile(BwdSmem<TILE, DEPTH>& sm, const ViewTable& vt, i
            __builtin_amdgcn_ballot_w64(c_alpha)) == 0)
         return;
       const bool contrib = c_pos && c_pow && c_alpha;
-      // Gradient arithmetic, branch-free: a lane that does not contribute selects
-      // zeros, so its nine values are exactly 0 and its state is unchanged.
-      // 1 - alpha >= 0.01, so the hardware reciprocal (1 ulp) is safe here.
-      const float inv = __builtin_amdgcn_rcpf(1.f - alpha);
+      // Gradient arithmetic, branch-free: a lane that does not contribute takes
+      // alpha = 0, so 1 / (1 - 0) = 1 exactly, its T and D stay as they are and its
+      // nine values are zeros.  1 - alpha >= 0.01, so the hardware reciprocal
+      // (1 ulp) is safe here.
+      const float ac = contrib ? alpha : 0.f;
+      const float inv = __builtin_amdgcn_rcpf(1.f - ac);
       const float Tb = T * inv;  // transmittance before this record
-      T = contrib ? Tb : T;
-      const float w = contrib ? alpha * Tb : 0.f;
+      T = Tb;
+      const float w = ac * Tb;
       // dL/dalpha = T_before (dL/dout . rgb) - D / (1 - alpha); clamped alpha has
-      // zero derivative
+      // zero derivative, so the alpha factor of dpow is zero there
       const float cdot = fmaf(db, q2.z, fmaf(dg, q2.y, dr * q2.x));
-      const bool open = contrib && a_raw <= kAlphaMax;
-      const float dalpha = open ? fmaf(Tb, cdot, -D * inv) : 0.f;
+      const float ao = a_raw <= kAlphaMax ? ac : 0.f;
+      const float dalpha = fmaf(Tb, cdot, -D * inv);
       D = fmaf(w, cdot, D);
       // Per-pair sums whose (tile, Gaussian) totals give the screen gradients:
       // dpow dx, dpow dy (mean, after the conic is applied at the flush),
       // dpow dx^2, dpow dx dy, dpow dy^2 (conic), dpow (opacity: dL/do is the sum
       // of dalpha G = dpow / o over unclamped pairs, and dpow is zero on the
       // others), w dL/dout (colour).
-      const float dpow = dalpha * alpha;
+      const float dpow = dalpha * ao;
       const float ex = dpow * dx, ey = dpow * dy;
       float g[9];
       g[0] = ex;
@@ -568,7 +574,7 @@ __device__ inline void bwd_tile(BwdSmem<TILE, DEPTH>& sm, const ViewTable& vt, i
       g[7] = w * dg;
       g[8] = w * db;
       wave_reduce_add(g, reinterpret_cast<float*>(reinterpret_cast<char*>(part_lane) + s.off4),
-                      slot, hi8);
+                      slot);
     };
     // two slots in flight: the LDS reads of one overlap the arithmetic of the
     // other; list entries two at a time (k - 1, k with k odd: 8-byte aligned)

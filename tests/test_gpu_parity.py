@@ -423,5 +423,7 @@ def test_autograd_function_matches_render_bwd(P, ctx):
     imgs, frame = P.render_fwd(ctx, params, cams)
     g = P.render_bwd(ctx, frame, params, [w[0].contiguous(), w[1].contiguous()])
     torch.cuda.synchronize()
+    # the compositing backward adds its sums with float atomics (LDS and global),
+    # whose order varies from run to run: the two paths agree to rounding
     for t, r in zip(ts, g.tensors()):
-        assert torch.allclose(t.grad, r, rtol=1e-5, atol=1e-7)
+        assert float((t.grad - r).norm()) <= 1e-5 * float(r.norm()) + 1e-12

@@ -44,8 +44,8 @@ FLOP_PAIR_BWD = 50
 MEASURED_TRAFFIC = [
     {"kernel": "blend_bwd", "views": 4, "tile": 16, "lds_depth": 256, "flags": 3,
      "source": "paper_2509_05216_amd/csrc/blend.hip",
-     "sha256": "6948d1a68263e3a181b0eb7241c7989fcc39fdf3ea7f723e1a8173881fba4013",
-     "read_bytes": 3193.0e6, "write_bytes": 935.5e6},
+     "sha256": "808670bd5215374d321b897f2996791c5cb7983ef0f897ac63e78765b70ce32b",
+     "read_bytes": 3177.7e6, "write_bytes": 933.9e6},
 ]
 
 

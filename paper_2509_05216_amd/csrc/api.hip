@@ -246,6 +246,8 @@ static gs_status build_views(Frame& f, const gs_camera* cams, int nv, float* con
     d.cx = c.cx;
     d.cy = c.cy;
     d.znear = c.z_near;
+    d.limx = kGuard * (0.5 * (double)c.width / (double)c.fx);
+    d.limy = kGuard * (0.5 * (double)c.height / (double)c.fy);
     for (int k = 0; k < 3; ++k)  // camera centre -R^T t
       d.campos[k] = (float)(-((double)c.R[0 * 3 + k] * c.t[0] + (double)c.R[1 * 3 + k] * c.t[1] +
                               (double)c.R[2 * 3 + k] * c.t[2]));

@@ -50,10 +50,15 @@ enum Word {
   kWordCount = 16
 };
 
+// Guard band on t_x/t_z, t_y/t_z for the projection Jacobian: 1.3 times the
+// half field of view.
+constexpr double kGuard = 1.3;
+
 struct CamDev {
   float R[9];
   float t[3];
   float fx, fy, cx, cy, znear;
+  double limx, limy;  // guard-band limits kGuard (W / 2) / fx and kGuard (H / 2) / fy, float64
   float campos[3];
   int W, H, tiles_x, tiles_y;
   int tile_offset;  // first global tile id of the view

@@ -14,7 +14,6 @@ namespace isogs {
 namespace {
 
 constexpr double kLowpass = 0.3;  // EWA low-pass added to the 2-D covariance
-constexpr double kGuard = 1.3;    // guard band on t_x/t_z, t_y/t_z for the Jacobian
 
 // Real SH basis, degree <= 3, Condon-Shortley phase, m = -l..l.
 constexpr float kK0 = 0.28209479177387814f;   // 1/(2 sqrt(pi))
@@ -166,9 +165,10 @@ __device__ inline void view_cov(const R* mu, const R* Sig, const CamDev& c, Proj
   const R tz = p.visible ? p.t[2] : R(1);
   const R fx = (R)c.fx, fy = (R)c.fy;
   if constexpr (sizeof(R) == 8) {
-    // float64: the divisions of the definition (binning decisions follow them)
-    p.limx = R(kGuard) * (R(0.5) * (R)c.W / fx);
-    p.limy = R(kGuard) * (R(0.5) * (R)c.H / fy);
+    // float64: the divisions of the definition (binning decisions follow them);
+    // the guard-band limits, the same for every Gaussian, come with the camera
+    p.limx = c.limx;
+    p.limy = c.limy;
     p.xz = p.t[0] / tz;
     p.yz = p.t[1] / tz;
     p.u = fmin(fmax(p.xz, -p.limx), p.limx);
@@ -253,8 +253,10 @@ __device__ inline uint32_t alpha_box_bits(float A, float B, float C, float o) {
   const double det = (double)A * (double)C - (double)B * (double)B;
   if (!(lim >= 1.0f) || !(det > 0.0)) return 0xBC00BC00u;  // fp16 -1, -1
   const double c2 = 2.0 * ((double)logf(lim) + 1e-3);  // bound of dx^T Q dx, with margin
-  const float hw = (float)(sqrt(c2 * (double)C / det) * 1.01 + 1e-2);
-  const float hh = (float)(sqrt(c2 * (double)A / det) * 1.01 + 1e-2);
+  // the square roots in float32: their relative error (~1e-7) is far inside the margin
+  const double q = c2 / det;
+  const float hw = sqrtf((float)(q * (double)C)) * 1.01f + 1e-2f;
+  const float hh = sqrtf((float)(q * (double)A)) * 1.01f + 1e-2f;
   return half_bits_up(hw) | (half_bits_up(hh) << 16);
 }
 
@@ -317,7 +319,11 @@ __global__ __launch_bounds__(256) void k_preprocess_fwd(ParamsDev prm, ViewTable
     const double fmx = floor(p.mx), fmy = floor(p.my);
     const double cmx = fmin(fmax(fmx, -1073741824.0), 1073741824.0);
     const double cmy = fmin(fmax(fmy, -1073741824.0), 1073741824.0);
-    const float cA = (float)(p.c / p.det), cB = (float)(-p.b / p.det), cC = (float)(p.a / p.det);
+    // conic = (c, -b, a) / det through one float64 reciprocal: within a float64 ulp of
+    // the quotients, so the stored float32 values are the rounded quotients but for
+    // rare ties of the double rounding (no binning decision reads them)
+    const double idet = 1.0 / p.det;
+    const float cA = (float)(p.c * idet), cB = (float)(-p.b * idet), cC = (float)(p.a * idet);
     splat[o * 3 + 0] = make_float4(cA, cB, cC, opacity);
     splat[o * 3 + 1] = make_float4(__int_as_float((int)cmx), __int_as_float((int)cmy),
                                    (float)(0.5 - (p.mx - cmx)), (float)(0.5 - (p.my - cmy)));

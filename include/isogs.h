@@ -195,9 +195,13 @@ const char* gs_stage_name(int32_t stage);
 gs_status gs_orbit_cameras(int32_t n_views, float radius, float fov_y_deg,
                            int32_t width, int32_t height, gs_camera* out);
 
-/* Gaussians from isosurface points (Sec. III).  xyz: device float32 [3][n]
- * point coordinates.  Writes every array of `out` (device, caller-owned,
- * sized for n and out.sh_degree): means = points, the rest per `opts`. */
+/* Gaussians from isosurface points (Sec. III).  xyz: float32 [3][n] point
+ * coordinates in device or host memory; host points are copied to a context
+ * buffer and the call then synchronises `stream` (the array may be reused on
+ * return), device points are read by the kernel (asynchronous).  Writes every
+ * array of `out` (device, caller-owned, sized for n and out.sh_degree):
+ * means = points, the rest per `opts`.  Calls that share a context and pass
+ * host points must not overlap. */
 gs_status gs_init_from_points(gs_ctx* ctx, const float* xyz, int64_t n,
                               const gs_init_opts* opts, uint64_t seed,
                               gs_params out, void* stream);
@@ -355,6 +359,8 @@ typedef struct {
 
 gs_status gs_step_graph_create(gs_ctx* ctx, const gs_step_desc* desc, gs_graph** out,
                                void* stream);
+/* gs_step_graph_create with the measuring pass on the null stream. */
+gs_status gs_step_graph_capture(gs_ctx* ctx, const gs_step_desc* desc, gs_graph** out);
 /* Enqueue one replay on `stream` (asynchronous). */
 gs_status gs_step_graph_launch(gs_graph* graph, void* stream);
 /* Wait for the last replay; report the record count and whether it overflowed

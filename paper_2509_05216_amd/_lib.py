@@ -159,6 +159,7 @@ SIGNATURES = [
     ("gs_frame_export", C.c_int, [_P, C.c_int32, C.c_int32, _P, C.c_size_t, _P]),
     ("gs_frame_release", None, [_P]),
     ("gs_step_graph_create", C.c_int, [_P, C.POINTER(GsStepDesc), C.POINTER(_P), _P]),
+    ("gs_step_graph_capture", C.c_int, [_P, C.POINTER(GsStepDesc), C.POINTER(_P)]),
     ("gs_step_graph_launch", C.c_int, [_P, _P]),
     ("gs_step_graph_sync", C.c_int, [_P, C.POINTER(C.c_int32), C.POINTER(C.c_int64), _P]),
     ("gs_step_graph_run", C.c_int, [_P, C.POINTER(C.c_int64), _P]),

@@ -339,16 +339,25 @@ def adam_step(ctx, p, g, m, v, step, *, lr=None, betas=(0.9, 0.999), eps=1e-15,
 def init_from_points(ctx, xyz, sh_degree, *, log_scale=0.0, log_scale_jitter=0.0,
                      log_scale_range=None, random_quats=False, opacity_logit=0.1, sh_std=0.0,
                      seed=0, stream=None):
-    """Gaussians from (3, n) device points; returns Params."""
-    n = int(xyz.shape[1])
-    dev = xyz.device
+    """Gaussians from (3, n) points: a device tensor, or host data (a CPU tensor or a
+    numpy array, copied by the library); returns Params on the context's device."""
+    if isinstance(xyz, np.ndarray) or not xyz.is_cuda:
+        host = np.ascontiguousarray(xyz.numpy() if torch.is_tensor(xyz) else xyz, np.float32)
+        n = int(host.shape[1])
+        dev = torch.device("cuda", ctx.device)
+        ptr = host.ctypes.data_as(C.c_void_p)
+    else:
+        xyz = xyz.contiguous()
+        n = int(xyz.shape[1])
+        dev = xyz.device
+        ptr = _ptr(xyz)
     p = Params(torch.empty((3, n), device=dev), torch.empty((3, n), device=dev),
                torch.empty((4, n), device=dev), torch.empty((n,), device=dev),
                torch.empty(((sh_degree + 1) ** 2 * 3, n), device=dev), sh_degree)
     lo, hi = (log_scale_range if log_scale_range is not None else (0.0, 0.0))
     o = L.GsInitOpts(log_scale, log_scale_jitter, lo, hi, 1 if random_quats else 0,
                      opacity_logit, sh_std, 0)
-    L.check(L.lib().gs_init_from_points(ctx.handle, _ptr(xyz.contiguous()), n, C.byref(o),
+    L.check(L.lib().gs_init_from_points(ctx.handle, ptr, n, C.byref(o),
                                         C.c_uint64(seed), p.abi(), _stream(stream)))
     return p
 

@@ -348,6 +348,7 @@ static void ctx_free(gs_ctx* ctx) {
     ctx->loss_scratch = nullptr;
   }
   buf_free(ctx, ctx->dens_blk);
+  buf_free(ctx, ctx->init_xyz);
   if (ctx->dens_host != nullptr) (void)hipHostFree(ctx->dens_host);
   ctx->dens_host = nullptr;
   buf_free(ctx, ctx->iso_blk);
@@ -545,8 +546,28 @@ gs_status gs_init_from_points(gs_ctx* ctx, const float* xyz, int64_t n, const gs
   }
   gs_status st = set_device(ctx);
   if (st != GS_OK) return st;
-  StageTimer tm(ctx, ST_INIT, (hipStream_t)stream);
-  return launch_init_points(xyz, n, *opts, seed, out, (hipStream_t)stream);
+  const hipStream_t s = (hipStream_t)stream;
+  // the points may be host or device memory; host points are copied to a context
+  // buffer first (a pageable pointer is unknown to HIP: clear that query's error)
+  hipPointerAttribute_t attr{};
+  const hipError_t pe = hipPointerGetAttributes(&attr, xyz);
+  if (pe != hipSuccess) (void)hipGetLastError();
+  const bool on_device =
+      pe == hipSuccess && (attr.type == hipMemoryTypeDevice || attr.type == hipMemoryTypeManaged);
+  const float* src = xyz;
+  if (!on_device && n > 0) {
+    st = buf_ensure(ctx, ctx->init_xyz, (size_t)n * 3 * sizeof(float), s);
+    if (st != GS_OK) return st;
+    GS_HIP(hipMemcpyAsync(ctx->init_xyz.p, xyz, (size_t)n * 3 * sizeof(float),
+                          hipMemcpyHostToDevice, s));
+    src = (const float*)ctx->init_xyz.p;
+  }
+  {
+    StageTimer tm(ctx, ST_INIT, s);
+    st = launch_init_points(src, n, *opts, seed, out, s);
+  }
+  if (st == GS_OK && src != xyz) GS_HIP(hipStreamSynchronize(s));
+  return st;
 }
 
 gs_status gs_render_fwd(gs_ctx* ctx, gs_params params, const gs_camera* cams, int32_t n_views,

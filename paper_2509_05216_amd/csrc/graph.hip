@@ -218,6 +218,10 @@ gs_status gs_step_graph_create(gs_ctx* ctx, const gs_step_desc* desc, gs_graph**
   return GS_OK;
 }
 
+gs_status gs_step_graph_capture(gs_ctx* ctx, const gs_step_desc* desc, gs_graph** out) {
+  return gs_step_graph_create(ctx, desc, out, nullptr);
+}
+
 gs_status gs_step_graph_launch(gs_graph* g, void* stream) {
   if (g == nullptr || g->exec == nullptr) {
     set_error("gs_step_graph_launch: no captured graph");

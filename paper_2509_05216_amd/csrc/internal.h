@@ -167,6 +167,7 @@ struct Ctx {
   DevBuf dens_blk;                 // gs_densify: block totals and offsets
   uint32_t* dens_host = nullptr;   // gs_densify: pinned read-back of the totals
   DevBuf iso_blk;                  // gs_iso_extract: block totals and offsets
+  DevBuf init_xyz;                 // gs_init_from_points: device copy of host points
   unsigned long long* iso_host = nullptr;  // gs_iso_extract: pinned read-back of the count
   // set while a graph is being captured: no allocation, no stage events
   bool capturing = false;

@@ -74,6 +74,39 @@ def _eager_step(P, ctx, params, cams, targets, grads):
     return imgs, loss, dl
 
 
+def test_capture_entry_point_matches_create(P, ctx, scene):
+    """gs_step_graph_capture (measuring pass on the null stream) builds the same
+    step as gs_step_graph_create on the same description."""
+    import ctypes as C
+    from paper_2509_05216_amd import _lib as L
+    cams_d, cams = _mixed_views(P)
+    params = P.Params.from_numpy(scene.params)
+    rng = np.random.default_rng(6)
+    targets = [torch.tensor(rng.random((3, c.height, c.width)), dtype=torch.float32,
+                            device="cuda") for c in cams]
+    g = P.StepGraph(ctx, params, cams, targets, with_adam=False,
+                    render=dict(tile=16, lds_depth=128, flags=P.PERSISTENT | P.LONGEST_FIRST))
+    g.run()
+    torch.cuda.synchronize()
+    imgs = [t.clone() for t in g.images]
+    grads = [t.clone() for t in g.grads.tensors()]
+    loss = g.loss.item()
+    h = C.c_void_p()
+    L.check(L.lib().gs_step_graph_capture(ctx.handle, C.byref(g._desc), C.byref(h)))
+    try:
+        rec = C.c_int64()
+        for _ in range(2):
+            L.check(L.lib().gs_step_graph_run(h, C.byref(rec), P.core._stream(None)))
+            torch.cuda.synchronize()
+            for a, b in zip(g.images, imgs):
+                assert torch.equal(a, b)
+            assert abs(g.loss.item() - loss) < 1e-6
+            for a, b in zip(g.grads.tensors(), grads):
+                assert rel_l2(a.cpu().numpy(), b.cpu().numpy()) < 1e-5
+    finally:
+        L.lib().gs_step_graph_destroy(h)
+
+
 def test_graph_replays_match_eager(P, ctx, scene):
     cams_d, cams = _mixed_views(P)
     params = P.Params.from_numpy(scene.params)

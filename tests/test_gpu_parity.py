@@ -412,6 +412,19 @@ def test_init_from_points_matches_oracle(P, ctx):
         assert np.allclose(out["opacity_logits"], o["opacity_logits"])
 
 
+def test_init_from_host_points_matches_device_points(P, ctx):
+    """Host points (numpy, CPU tensor) are copied by the library: same Gaussians."""
+    rng = np.random.default_rng(12)
+    xyz = rng.uniform(-1, 1, (3, 3001)).astype(np.float32)
+    kw = dict(log_scale=-4.0, log_scale_jitter=0.5, random_quats=True, sh_std=0.1, seed=77)
+    ref = P.init_from_points(ctx, torch.tensor(xyz, device="cuda"), 3, **kw)
+    for host in (xyz, torch.tensor(xyz)):
+        got = P.init_from_points(ctx, host, 3, **kw)
+        torch.cuda.synchronize()
+        for a, b in zip(got.tensors(), ref.tensors()):
+            assert torch.equal(a, b)
+
+
 def test_autograd_function_matches_render_bwd(P, ctx):
     scene = gsscenes.make_scene("tiny", n=1500)
     cams = [P.camera_from_dict(c) for c in _cams(2, 96, 96)]

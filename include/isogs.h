@@ -25,6 +25,10 @@
  *    to GS_ERR_HIP, capacity overruns to GS_ERR_CAPACITY.
  *  - Objects created by the library (contexts, frames, graphs, servers) are
  *    owned by it and freed by their *_destroy / *_release call.
+ *  - Some calls keep scratch in the context (noted at each: the loss
+ *    workspace, the densify and extraction block totals and read-backs, the
+ *    host-point copy); such calls on one context must not overlap.  A frame
+ *    is used by one call at a time.
  */
 #ifndef ISOGS_H
 #define ISOGS_H
@@ -495,8 +499,9 @@ typedef struct {
  * = NULL to only count (info filled, nothing written).  src_index (optional,
  * device int32[n_out]) receives the source index of every output.  The
  * statistics and inputs are read, not changed.  Synchronises `stream` once
- * (the counts are read back).  GS_ERR_CAPACITY when p_out.n < n_out,
- * GS_ERR_INVALID when larger. */
+ * (the counts are read back through context scratch: calls on one context
+ * must not overlap).  GS_ERR_CAPACITY when p_out.n < n_out, GS_ERR_INVALID
+ * when larger. */
 gs_status gs_densify(gs_ctx* ctx, gs_params p, gs_params m, gs_params v,
                      gs_density_stats stats, const gs_density_opts* opts, gs_params p_out,
                      gs_params m_out, gs_params v_out, int32_t* src_index,
@@ -529,7 +534,8 @@ typedef struct {
  * high), is below keep_prob (1: all).  *n_points receives the number kept;
  * with xyz (device float32 [3][capacity]) non-NULL they are written there
  * (GS_ERR_CAPACITY, nothing written, if they do not fit).  Synchronises
- * `stream` once (the count is read back). */
+ * `stream` once (the count is read back through context scratch: calls on one
+ * context must not overlap). */
 gs_status gs_iso_extract(gs_ctx* ctx, gs_volume volume, float iso, float keep_prob,
                          uint64_t seed, float* xyz, int64_t capacity, int64_t* n_points,
                          void* stream);

@@ -671,7 +671,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
-              "split is not part of this build", file=sys.stderr)
+              "split is not implemented here", file=sys.stderr)
         sys.exit(2)
     import torch
 
@@ -756,7 +756,7 @@ def main():
         frame.release()
     # device memory of the training step (before the Adam and copy-probe legs allocate
     # their own buffers): the library's buffers (current and high-water), the caller's
-    # tensors (torch's high-water mark) and the device's use as the driver reports it
+    # tensors (torch's high-water mark) and the device's use as the HIP runtime reports it
     lib_now, lib_peak = ctx.memory()
     free_b, total_b = torch.cuda.mem_get_info()
     memory = {"library_bytes": lib_now, "library_peak_bytes": lib_peak,

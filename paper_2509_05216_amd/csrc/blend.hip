@@ -34,19 +34,22 @@
 // per-pair use/stop decisions are scalar operations on comparison ballots; the
 // backward's flush transforms each slot's sums in place before the global
 // atomics.  A staged splat carries its conic pre-scaled by -log2(e)/2 (one
-// fused quadratic and one v_exp per pair) and its mean relative to the tile
-// origin.  Both kernels
-// evaluate the skip/stop decisions with the same inline code on the same
-// staged values (the library is compiled with -ffp-contract=off, and the
-// fused operations are explicit), so the backward reproduces the forward's
-// decisions exactly.
+// fused quadratic and one v_exp per pair), log2 of its opacity in place of the
+// opacity (one v_log per staged splat), so that pa = p2 + log2 o is log2 of
+// o G: the alpha test o G >= 1/255 becomes pa >= -log2 255, taken before any
+// v_exp (a backward pair the test rejects costs none; the log-domain test
+// agrees with the linear one except within about 1e-6 of the threshold), and
+// alpha = 2^pa.  Its mean is stored relative to the tile origin.  Both kernels evaluate the skip/stop decisions with the same
+// inline code on the same staged values (the library is compiled with
+// -ffp-contract=off, and the fused operations are explicit), so the backward
+// reproduces the forward's decisions exactly.
 #include "internal.h"
 
 namespace isogs {
 namespace {
 
-constexpr float kAlphaMin = 1.0f / 255.0f;
 constexpr float kAlphaMax = 0.99f;
+constexpr float kLog2AlphaMin = -7.99435343685885793f;  // log2(1/255)
 constexpr float kTMin = 1e-4f;
 
 // Staged form of a splat: the conic scaled so that one fused quadratic gives
@@ -97,10 +100,13 @@ __device__ inline bool box_misses(float4 b, int bx0, int by0) {
 template <int NT, int DEPTH>
 struct Stage {
   static constexpr int NW = NT / 64;
-  // 16 bytes per slot in every array, so one shifted index addresses all three
-  float4 s0[DEPTH];  // scaled conic (a, b, c), opacity
-  float4 s1[DEPTH];  // mean relative to the tile origin (x, y), 4 x slot as bits (z), unused (w)
-  float4 s2[DEPTH];  // rgb
+  // 16 bytes per slot in every array, so one shifted index addresses all three.
+  // The walks read 16 + 16 + 4 (forward) or 16 + 16 + 8 (backward) bytes per
+  // slot: 12-byte LDS reads measured slower than 8- and 16-byte ones here
+  // (layouts that read the colour or the mean quad as 12 bytes took 2-3% longer).
+  float4 s0[DEPTH];  // scaled conic (a, b, c), log2 of the opacity
+  float4 s1[DEPTH];  // mean relative to the tile origin (x, y), red, green
+  float4 s2[DEPTH];  // blue, 4 x slot as bits (the slot's sum-table column), unused
   uint32_t sidx[DEPTH];
   // per wave: byte offsets (16 x slot) of the overlapping slots in ascending
   // order, then four zero entries, so that reads of up to four entries past the
@@ -125,11 +131,12 @@ __device__ inline void stage_batch(Stage<TILE * TILE, DEPTH>& st, const uint32_t
     const float4 q0 = splat[(size_t)idx * 3 + 0], q1 = splat[(size_t)idx * 3 + 1];
     const float4 q2 = splat[(size_t)idx * 3 + 2];
     st.sidx[t] = idx;
-    st.s0[t] = make_float4(q0.x * (-0.5f * kLog2e), q0.y * -kLog2e, q0.z * (-0.5f * kLog2e), q0.w);
+    st.s0[t] = make_float4(q0.x * (-0.5f * kLog2e), q0.y * -kLog2e, q0.z * (-0.5f * kLog2e),
+                           __builtin_amdgcn_logf(q0.w));  // log2 o (-inf for o = 0)
     st.s1[t] = make_float4((float)(__float_as_int(q1.x) - tile_x0) - q1.z,
                            (float)(__float_as_int(q1.y) - tile_y0) - q1.w,
-                           __uint_as_float((uint32_t)t * 4u), 0.f);
-    st.s2[t] = q2;  // rgb; the walks do not read .w (the packed box)
+                           q2.x, q2.y);
+    st.s2[t] = make_float4(q2.z, __uint_as_float((uint32_t)t * 4u), 0.f, 0.f);
     const float4 b = splat_box(q1, q2);
 #pragma unroll
     for (int w = 0; w < NW; ++w)
@@ -185,7 +192,7 @@ struct Layout {
 struct Slot {
   uint32_t off;   // 16 x slot index
   uint32_t off4;  // 4 x slot index (byte offset of the slot's column in the sum table)
-  float4 q0;      // scaled conic, opacity
+  float4 q0;      // scaled conic, log2 of the opacity
   float2 m;       // tile-relative mean
   float3 q2;      // rgb
 };
@@ -197,9 +204,9 @@ __device__ inline Slot load_slot(const Stage<NT, DEPTH>& st, uint32_t off) {
   s.q0 = *reinterpret_cast<const float4*>(reinterpret_cast<const char*>(st.s0) + off);
   const float4 m = *reinterpret_cast<const float4*>(reinterpret_cast<const char*>(st.s1) + off);
   s.m = make_float2(m.x, m.y);
-  s.off4 = __float_as_uint(m.z);
   const float4 c = *reinterpret_cast<const float4*>(reinterpret_cast<const char*>(st.s2) + off);
-  s.q2 = make_float3(c.x, c.y, c.z);
+  s.off4 = __float_as_uint(c.y);
+  s.q2 = make_float3(m.z, m.w, c.x);
   return s;
 }
 
@@ -238,9 +245,11 @@ __device__ inline void fwd_tile(Stage<TILE * TILE, DEPTH>& st, const ViewTable& 
     auto step = [&](const Slot& s) {
       float dx, dy;
       const float p2 = pair_eval(s.q0, s.m, rx, ry, dx, dy);
-      const float alpha = fminf(kAlphaMax, s.q0.w * __builtin_amdgcn_exp2f(p2));
+      const float pa = p2 + s.q0.w;  // log2 (o G)
+      // alpha ahead of the test (its v_exp overlaps the ballots)
+      const float alpha = fminf(kAlphaMax, __builtin_amdgcn_exp2f(pa));
       uint64_t m_use = ~done_m & __builtin_amdgcn_ballot_w64(!(p2 > 0.f)) &
-                       __builtin_amdgcn_ballot_w64(!(alpha < kAlphaMin));
+                       __builtin_amdgcn_ballot_w64(pa >= kLog2AlphaMin);
       if (m_use == 0) return;  // no lane takes this splat: nothing changes
       // weight alpha T and the transmittance after, T - alpha T = T (1 - alpha)
       const float wa = alpha * T;
@@ -529,17 +538,17 @@ __device__ inline void bwd_tile(BwdSmem<TILE, DEPTH>& sm, const ViewTable& vt, i
       // the skip decisions are the forward's, from the same expressions
       float dx, dy;
       const float p2 = pair_eval(s.q0, s.m, rx, ry, dx, dy);
-      const float G = __builtin_amdgcn_exp2f(p2);
-      const float a_raw = s.q0.w * G;
-      const float alpha = fminf(kAlphaMax, a_raw);
+      const float pa = p2 + s.q0.w;  // log2 (o G)
       // nc = 0 outside the image, so the first test also covers the image bounds;
       // one ballot per comparison keeps the wave test on the comparison masks
       const bool c_pos = s.off4 < ncb;
       const bool c_pow = !(p2 > 0.f);
-      const bool c_alpha = !(alpha < kAlphaMin);
+      const bool c_alpha = pa >= kLog2AlphaMin;
       if ((__builtin_amdgcn_ballot_w64(c_pos) & __builtin_amdgcn_ballot_w64(c_pow) &
            __builtin_amdgcn_ballot_w64(c_alpha)) == 0)
         return;
+      const float a_raw = __builtin_amdgcn_exp2f(pa);  // o G
+      const float alpha = fminf(kAlphaMax, a_raw);
       const bool contrib = c_pos && c_pow && c_alpha;
       // Gradient arithmetic, branch-free: a lane that does not contribute takes
       // alpha = 0, so 1 / (1 - 0) = 1 exactly, its T and D stay as they are and its
@@ -616,11 +625,11 @@ __device__ inline void bwd_tile(BwdSmem<TILE, DEPTH>& sm, const ViewTable& vt, i
       part[2 * kPart + j] *= -0.5f;
       part[3 * kPart + j] *= -1.f;
       part[4 * kPart + j] *= -0.5f;
-      // a nonzero sum comes from contributing pairs, whose opacity is >= 1/255 (the
-      // alpha test), so the 1-ulp reciprocal is finite; a zero sum stays zero
-      // whatever the opacity (no 0 * inf at an opacity that underflowed to 0)
+      // a nonzero sum comes from contributing pairs, whose opacity is >= about
+      // 1/255 (the alpha test), so 1/o = 2^-log2(o) is finite; a zero sum stays
+      // zero whatever the opacity (no 0 * inf at an opacity that underflowed to 0)
       const float e5 = part[5 * kPart + j];
-      part[5 * kPart + j] = e5 != 0.f ? e5 * __builtin_amdgcn_rcpf(q.w) : 0.f;
+      part[5 * kPart + j] = e5 != 0.f ? e5 * __builtin_amdgcn_exp2f(-q.w) : 0.f;
     }
     __syncthreads();
     // then the atomics, (slot, component) interleaved: the six geometric sums

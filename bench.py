@@ -44,8 +44,8 @@ FLOP_PAIR_BWD = 50
 MEASURED_TRAFFIC = [
     {"kernel": "blend_bwd", "views": 4, "tile": 16, "lds_depth": 256, "flags": 3,
      "source": "paper_2509_05216_amd/csrc/blend.hip",
-     "sha256": "808670bd5215374d321b897f2996791c5cb7983ef0f897ac63e78765b70ce32b",
-     "read_bytes": 3177.7e6, "write_bytes": 933.9e6},
+     "sha256": "2f85b94845b9ffc043e6f77509bfbd8f03c97cadbcdf174e1f0596f37f1a42b7",
+     "read_bytes": 3174.1e6, "write_bytes": 933.9e6},
 ]
 
 

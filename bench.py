@@ -76,6 +76,9 @@ def parse():
     ap.add_argument("--tile", type=int, default=16)
     ap.add_argument("--lds-depth", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--wide", action="store_true",
+                    help="also time the 4M scene with log-scales U(-5,-3) (splat-size sensitivity; "
+                         "about a minute)")
     ap.add_argument("--only", choices=["all", "batched", "plain"], default="all")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-train", action="store_true", help="skip the 1M-Gaussian training run")
@@ -141,6 +144,47 @@ def run_graph(P, ctx, params, cams, targets, steps, warmup, render, with_adam, t
     cap, _ = g.info()
     g.close()
     return t, rec, cap, loss
+
+
+def wide_scales(P, ctx, params, cams, targets, steps, warmup, torch):
+    """The 4M scene with every log-scale drawn from U(-5, -3) instead of log(h) +- 0.5
+    (seeded; splats of several to tens of pixels, far longer tile lists): the batched
+    step timed as graph replays for a few render options (no autotuning: one step takes
+    hundreds of milliseconds), for the sensitivity of the step to splat size."""
+    rng = np.random.default_rng(20_000)
+    n = params.n
+    wide = P.Params(params.means, torch.tensor(rng.uniform(-5.0, -3.0, (3, n)).astype(np.float32),
+                                               device="cuda"),
+                    params.quats, params.opacity_logits, params.sh, params.sh_degree)
+    pixels = sum(c.width * c.height for c in cams)
+    frame = P.Frame()
+    images = [torch.empty((3, c.height, c.width), device="cuda") for c in cams]
+    P.render_fwd(ctx, wide, cams, images, frame=frame)
+    st = frame.stats()
+    frame.release()
+    log(f"wide-scale 4M scene: K={st['n_records']}, {st['n_visible']} visible entries")
+    rows = []
+    # tile 16 and 32 (at tile 8 the records pass three billion)
+    for render in ({"tile": 16, "lds_depth": 256, "flags": 3}, {"tile": 32, "lds_depth": 256, "flags": 3}):
+        try:
+            gtm, rec, cap, gloss = run_graph(P, ctx, wide, cams, targets, steps, warmup, render,
+                                             False, torch)
+        except P.IsogsError as e:  # e.g. more records than a frame holds at small tiles
+            rows.append({**render, "error": str(e)})
+            log(f"wide-scale 4M step {render}: {e}")
+            continue
+        ms = gtm["median"]
+        rows.append({**render, "ms_per_step": round(ms, 3),
+                     "mpix_per_s": round(pixels / (ms * 1e-3) / 1e6, 3), "loss": round(gloss, 6)})
+        log(f"wide-scale 4M step {render}: {ms:.1f} ms")
+    best = min((r for r in rows if "ms_per_step" in r), key=lambda r: r["ms_per_step"])
+    return {"ms_per_step": best["ms_per_step"], "mpix_per_s": best["mpix_per_s"],
+            "records_K": st["n_records"], "visible": st["n_visible"],
+            "tiles_per_entry": round(st["n_records"] / max(st["n_visible"], 1), 3),
+            "options": rows,
+            "workload": ("kingsnake4m points, log-scales U(-5,-3) per axis (seeded), SH3; the "
+                         "headline's 4 views per step, one hipGraph replay per step, the faster "
+                         "of tile 16 and tile 32 (persistent longest-first, LDS depth 256)")}
 
 
 def run_steps(P, ctx, params, cams, targets, steps, warmup, tile, depth, torch, flags=0):
@@ -843,6 +887,7 @@ def main():
                       "ms_stats": {a: round(b, 4) for a, b in r["timing"].items()},
                       "mpix_per_s": round(r["pixels"] / (r["ms"] * 1e-3) / 1e6, 3),
                       "records_K": r["K"], "visible": r["visible"], "pairs": r["pairs"],
+                      "tiles_per_entry": round(r["K"] / max(r["visible"], 1), 3),
                       "loss": round(r["loss"], 6),
                       **({"ms_with_adam": round(r["ms_with_adam"], 3), "capacity": r["capacity"]}
                          if "ms_with_adam" in r else {}),
@@ -858,6 +903,13 @@ def main():
         "hbm_probe": {"GBps": round(probe_gbs, 1), "bytes_per_launch": 2 * probe_bytes,
                       "ms": round(probe_ms, 4), "frac_of_peak": round(probe_gbs / HBM_PEAK_GBS, 4)},
     }
+    if args.wide and args.workload == "kingsnake4m" and args.only in ("all", "batched"):
+        t0 = time.perf_counter()
+        wsc = wide_scales(P, ctx, params, cams, targets, min(args.steps, 5), min(args.warmup, 2),
+                          torch)
+        out["forms"]["batched_graph_wide_scales"] = wsc
+        log(f"wide-scale 4M step: {wsc['ms_per_step']:.2f} ms, {wsc['mpix_per_s']:.0f} Mpix/s, "
+            f"K={wsc['records_K']} ({time.perf_counter() - t0:.1f}s)")
     if not args.no_train and args.workload == "kingsnake4m":
         t0 = time.perf_counter()
         out["train_c1"] = train_c1(P, ctx, torch, iters=args.train_iters)

@@ -45,7 +45,9 @@ typedef enum {
   GS_ERR_INVALID = -1,     /* bad argument (null pointer, size out of range) */
   GS_ERR_NOMEM = -2,       /* device memory or the context budget exhausted */
   GS_ERR_HIP = -3,         /* a HIP runtime call failed */
-  GS_ERR_CAPACITY = -4,    /* more (Gaussian, tile) records than fit */
+  GS_ERR_CAPACITY = -4,    /* more (Gaussian, tile) records than fit: a frame holds at
+                              most 2^32 - 2^20 records and as many (view, Gaussian)
+                              entries */
   GS_ERR_UNSUPPORTED = -5, /* device is not gfx950, or option not supported */
   GS_ERR_BUSY = -6         /* object in use (server queue full, ...) */
 } gs_status;

@@ -589,8 +589,8 @@ gs_status gs_render_fwd(gs_ctx* ctx, gs_params params, const gs_camera* cams, in
       return GS_ERR_INVALID;
     }
   }
-  if ((uint64_t)n_views * (uint64_t)params.n >= 0xffffffffULL) {
-    set_error("gs_render_fwd: n_views * n exceeds 2^32 - 1");
+  if ((uint64_t)n_views * (uint64_t)params.n > kMaxRecords) {
+    set_error("gs_render_fwd: n_views * n exceeds %llu", (unsigned long long)kMaxRecords);
     return GS_ERR_CAPACITY;
   }
   int tile = 16, depth = 256, flags = 0;
@@ -690,8 +690,9 @@ gs_status gs_render_fwd_multi(gs_ctx* ctx, const gs_params* params, const gs_cam
     }
     total += (uint64_t)params[v].n;
   }
-  if (total >= 0xffffffffULL) {
-    set_error("gs_render_fwd_multi: the views' Gaussian counts sum past 2^32 - 1");
+  if (total > kMaxRecords) {
+    set_error("gs_render_fwd_multi: the views' Gaussian counts sum past %llu",
+              (unsigned long long)kMaxRecords);
     return GS_ERR_CAPACITY;
   }
   int tile = 16, depth = 256, flags = 0;
@@ -859,9 +860,9 @@ gs_status forward_stages(Ctx* ctx, Frame& f, const ParamsDev& pd, hipStream_t s,
     GS_HIP(hipStreamSynchronize(s));
     const uint64_t K = f.pinned[0];
     f.visible = (int64_t)(uint32_t)f.pinned[1];
-    if (K >= 0xffffffffULL) {
-      set_error("gs_render_fwd: %llu (Gaussian, tile) records exceed 2^32 - 1",
-                (unsigned long long)K);
+    if (K > kMaxRecords) {
+      set_error("gs_render_fwd: %llu (Gaussian, tile) records exceed the limit of %llu",
+                (unsigned long long)K, (unsigned long long)kMaxRecords);
       return GS_ERR_CAPACITY;
     }
     f.K = (int64_t)K;

@@ -137,7 +137,7 @@ gs_status reserve_and_capture(gs_graph* g) {
 
 uint32_t capacity_for(uint64_t K, double slack) {
   const double c = std::max((double)K * slack, (double)K + 65536.0);
-  return (uint32_t)std::min(c, 4294967000.0);
+  return (uint32_t)std::min(c, (double)kMaxRecords);
 }
 
 }  // namespace
@@ -252,8 +252,9 @@ gs_status gs_step_graph_sync(gs_graph* g, int32_t* overflowed, int64_t* records,
   if (records) *records = (int64_t)total;
   if (overflowed) *overflowed = over ? 1 : 0;
   if (over) {
-    if (total >= 0xffffffffULL) {
-      set_error("gs_step_graph_sync: %llu records exceed 2^32 - 1", (unsigned long long)total);
+    if (total > kMaxRecords) {
+      set_error("gs_step_graph_sync: %llu records exceed the limit of %llu",
+                (unsigned long long)total, (unsigned long long)kMaxRecords);
       return GS_ERR_CAPACITY;
     }
     g->cap = capacity_for(total, g->slack);

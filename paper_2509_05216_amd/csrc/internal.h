@@ -33,6 +33,11 @@ constexpr int kMaxViews = 16;
 // opacity) + 2 pad floats, then (after all geometric records) the colour sums
 // dL/d(r, g, b) + 1 pad float.  The projection backward's geometry and colour
 // kernels each read (and clear) only their own array.
+// Largest record count of a frame: the sort kernels index records with 32-bit
+// integers and round grids up to 4096-record chunks, so the count stays 2^20
+// below 2^32 (every index + chunk offset then fits).
+constexpr uint64_t kMaxRecords = 0xFFF00000ull;
+
 constexpr int kAccG = 8;
 constexpr int kAccC = 4;
 constexpr int kAccStride = kAccG + kAccC;  // floats per (view, Gaussian) in total

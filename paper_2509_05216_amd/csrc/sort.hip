@@ -472,7 +472,9 @@ __global__ __launch_bounds__(256) void k_export_keys(const uint32_t* __restrict_
   out[k] = ((uint64_t)tkey[k] << 32) | (uint64_t)dkey[tval[k]];
 }
 
-inline uint32_t nblocks_of(uint32_t n) { return (n + kChunk - 1) / kChunk; }
+inline uint32_t nblocks_of(uint32_t n) {
+  return (uint32_t)(((uint64_t)n + kChunk - 1) / kChunk);
+}
 
 // The scanned digit table of a sort's last pass holds, at (digit d, chunk 0),
 // the number of keys whose top byte is below d.  After a depth sort (positive

@@ -138,3 +138,27 @@ def test_server_first_batches_on_fresh_slots(P):
         for (t, out), ref in zip(tickets, refs):
             assert torch.equal(out, ref), trial
         srv.close()
+
+
+def test_entry_limit_is_checked_before_any_launch(P):
+    """views x Gaussians past the frame's entry limit (2^32 - 2^20) is rejected with
+    GS_ERR_CAPACITY on the host, before the parameters are touched (the count is set
+    in the ABI struct; the arrays hold one Gaussian)."""
+    from paper_2509_05216_amd import _lib as L
+    from paper_2509_05216_amd.core import _cam_array, _opts
+    ctx = P.Context(0)
+    small = P.Params.from_numpy(gsscenes.make_scene("tiny", n=1000).params)
+    ab = small.abi()
+    ab.n = 1 << 28                           # 16 views x 2^28 = 2^32 > the limit
+    cams = [P.camera_from_dict(c) for c in
+            [ocam.to_float32(x) for x in ocam.orbit_cameras(16, 2.5, 60.0, 64, 64)]]
+    imgs = [torch.empty((3, 64, 64), device="cuda") for _ in cams]
+    pa, keep = L.ptr_array([t.data_ptr() for t in imgs])
+    o = _opts(16, 256, (0.0, 0.0, 0.0), 0)
+    fr = C.c_void_p()
+    st = L.lib().gs_render_fwd(ctx.handle, ab, _cam_array(cams), 16, pa, C.byref(o),
+                               C.byref(fr), None)
+    assert st == -4, L.lib().gs_last_error()
+    assert b"exceeds" in L.lib().gs_last_error()
+    assert not fr.value
+    ctx.close()

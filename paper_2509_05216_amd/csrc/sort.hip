@@ -81,13 +81,35 @@ __global__ __launch_bounds__(kThreads) void k_scan_reduce(F f, uint32_t n, uint6
   if (threadIdx.x == 0) partial[blockIdx.x] = total;
 }
 
-// Down-sweep: each block forms its carry-in by summing the totals of the
-// blocks before it (a few thousand at most, read from L2), so no separate
-// single-block scan of the totals is launched; the last block also writes the
-// grand total when d_total is given.
+// Exclusive scan, in place, of the nb block totals by one block (each thread a
+// contiguous run); the grand total goes to d_total when given.  Used when there
+// are too many blocks for the down-sweep to sum its predecessors itself.
+__global__ __launch_bounds__(kThreads) void k_scan_partials(uint64_t* partial, uint32_t nb,
+                                                            uint64_t* d_total) {
+  __shared__ uint64_t sw[kWaves];
+  const uint32_t per = (nb + kThreads - 1) / kThreads;
+  const uint32_t lo = min(nb, threadIdx.x * per), hi = min(nb, lo + per);
+  uint64_t s = 0;
+  for (uint32_t j = lo; j < hi; ++j) s += partial[j];
+  uint64_t total;
+  uint64_t run = block_exclusive_scan(s, sw, total);
+  for (uint32_t j = lo; j < hi; ++j) {
+    const uint64_t v = partial[j];
+    partial[j] = run;
+    run += v;
+  }
+  if (d_total != nullptr && threadIdx.x == 0) *d_total = total;
+}
+
+// Down-sweep.  With few blocks each forms its carry-in by summing the totals of
+// the blocks before it (read from L2), so no separate scan of the totals is
+// launched, and the last block writes the grand total when d_total is given;
+// with many (prescanned), k_scan_partials has already turned the totals into
+// the carries and written the grand total.
 template <class F>
 __global__ __launch_bounds__(kThreads) void k_scan_down(F f, uint32_t n, const uint64_t* partial,
-                                                        uint32_t* out, uint64_t* d_total) {
+                                                        uint32_t* out, uint64_t* d_total,
+                                                        int prescanned) {
   __shared__ uint64_t sw[kWaves];
   // striped (coalesced) loads and stores, transposed through LDS so that each
   // thread scans kItems consecutive elements; one pad word per 32 avoids bank conflicts
@@ -108,13 +130,18 @@ __global__ __launch_bounds__(kThreads) void k_scan_down(F f, uint32_t n, const u
     v[j] = buf[p + (p >> 5)];
     s += v[j];
   }
-  uint64_t carry = 0;
-  for (uint32_t b = threadIdx.x; b < blockIdx.x; b += kThreads) carry += partial[b];
   uint64_t ctot;
-  block_exclusive_scan(carry, sw, ctot);  // ctot: the sum over all threads
+  if (prescanned) {
+    ctot = partial[blockIdx.x];
+  } else {
+    uint64_t carry = 0;
+    for (uint32_t b = threadIdx.x; b < blockIdx.x; b += kThreads) carry += partial[b];
+    block_exclusive_scan(carry, sw, ctot);  // ctot: the sum over all threads
+  }
   uint64_t total;
   uint64_t run = block_exclusive_scan(s, sw, total) + ctot;
-  if (d_total != nullptr && blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) *d_total = ctot + total;
+  if (!prescanned && d_total != nullptr && blockIdx.x == gridDim.x - 1 && threadIdx.x == 0)
+    *d_total = ctot + total;
 #pragma unroll
   for (int j = 0; j < kItems; ++j) {
     const uint32_t p = threadIdx.x * kItems + j;
@@ -498,6 +525,27 @@ gs_status launch_fill_u32(void* p, uint32_t value, size_t count, hipStream_t s) 
   return GS_OK;
 }
 
+// Exclusive scan of f over n values into out (in place when out is f's array):
+// block totals, then either the down-sweep summing its predecessors (up to
+// kDirectBlocks blocks) or a one-block scan of the totals first.
+constexpr uint32_t kDirectBlocks = 2048;
+
+static gs_status scan_launch(ArrayIn f, uint32_t n, uint64_t* partial, uint32_t* out,
+                             uint64_t* d_total, hipStream_t s) {
+  const uint32_t nb = nblocks_of(n);
+  hipLaunchKernelGGL(k_scan_reduce<ArrayIn>, dim3(nb), dim3(kThreads), 0, s, f, n, partial);
+  GS_LAUNCHED("scan_reduce");
+  const int pre = nb > kDirectBlocks ? 1 : 0;
+  if (pre) {
+    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kThreads), 0, s, partial, nb, d_total);
+    GS_LAUNCHED("scan_partials");
+  }
+  hipLaunchKernelGGL(k_scan_down<ArrayIn>, dim3(nb), dim3(kThreads), 0, s, f, n,
+                     (const uint64_t*)partial, out, d_total, pre);
+  GS_LAUNCHED("scan_down");
+  return GS_OK;
+}
+
 static gs_status ensure_scratch(Ctx* ctx, SortScratch& ss, uint32_t nb, size_t hist_entries,
                                 hipStream_t s) {
   gs_status st = buf_ensure(ctx, ss.partial, sizeof(uint64_t) * (size_t)(nb + 1), s, ss.prior);
@@ -517,14 +565,7 @@ gs_status scan_tile_counts(Ctx* ctx, SortScratch& ss, const uint32_t* sidx, cons
   hipLaunchKernelGGL(k_counts, dim3((n + 255) / 256), dim3(256), 0, s, sidx, rect, n, offs, srx,
                      sry);
   GS_LAUNCHED("counts");
-  ArrayIn f{offs};
-  auto* partial = (uint64_t*)ss.partial.p;
-  hipLaunchKernelGGL(k_scan_reduce<ArrayIn>, dim3(nb), dim3(kThreads), 0, s, f, n, partial);
-  GS_LAUNCHED("scan_reduce");
-  hipLaunchKernelGGL(k_scan_down<ArrayIn>, dim3(nb), dim3(kThreads), 0, s, f, n, partial, offs,
-                     d_total);
-  GS_LAUNCHED("scan_down");
-  return GS_OK;
+  return scan_launch(ArrayIn{offs}, n, (uint64_t*)ss.partial.p, offs, d_total, s);
 }
 
 gs_status sort_pairs_u32(Ctx* ctx, SortScratch& ss, const uint32_t* kin, const uint32_t* vin,
@@ -547,12 +588,8 @@ gs_status sort_pairs_u32(Ctx* ctx, SortScratch& ss, const uint32_t* kin, const u
   for (int shift = 0; shift < bits; shift += 8) {
     hipLaunchKernelGGL(k_radix_hist, dim3(nb), dim3(kThreads), 0, s, ki, n, d_n, shift, nb, hist);
     GS_LAUNCHED("radix_hist");
-    ArrayIn f{hist};
-    hipLaunchKernelGGL(k_scan_reduce<ArrayIn>, dim3(hb), dim3(kThreads), 0, s, f, hist_n, partial);
-    GS_LAUNCHED("radix_scan_reduce");
-    hipLaunchKernelGGL(k_scan_down<ArrayIn>, dim3(hb), dim3(kThreads), 0, s, f, hist_n, partial,
-                       hist, (uint64_t*)nullptr);
-    GS_LAUNCHED("radix_scan_down");
+    st = scan_launch(ArrayIn{hist}, hist_n, partial, hist, nullptr, s);
+    if (st != GS_OK) return st;
     hipLaunchKernelGGL(k_radix_scatter, dim3(nb), dim3(kThreads), 0, s, ki, vi, kb[out], vb[out],
                        n, d_n, shift, nb, hist);
     GS_LAUNCHED("radix_scatter");

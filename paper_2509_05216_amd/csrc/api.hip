@@ -302,7 +302,7 @@ static gs_status frame_buffers(Frame& f, hipStream_t s) {
   ENS(f.finalT, (size_t)f.total_pix * 4);
   ENS(f.ncon, (size_t)f.total_pix * 4);
   if (f.keep_radii) ENS(f.radii, vn * 4);
-  if (!f.multi && f.views > 1) {
+  if (!f.multi) {  // the projection backward's side stream and mean scratch
     ENS(f.gmu, (size_t)f.n * 12);
     if (f.side == nullptr) {
       GS_HIP(hipStreamCreateWithFlags(&f.side, hipStreamNonBlocking));

@@ -48,49 +48,6 @@ __device__ inline void sh_basis(float x, float y, float z, int deg, float* Y) {
   Y[15] = -kA3 * x * (xx - 3.f * yy);
 }
 
-// d/d(x, y, z) of each basis polynomial, accumulated against weights w[j]:
-// g += sum_j w[j] * grad Y_j.
-__device__ inline void sh_basis_grad_dot(float x, float y, float z, int deg, const float* w,
-                                         float& gx, float& gy, float& gz) {
-  if (deg < 1) return;
-  gy += -kK1 * w[1];
-  gz += kK1 * w[2];
-  gx += -kK1 * w[3];
-  if (deg < 2) return;
-  const float xx = x * x, yy = y * y, zz = z * z;
-  gx += kK2 * y * w[4];
-  gy += kK2 * x * w[4];
-  gy += -kK2 * z * w[5];
-  gz += -kK2 * y * w[5];
-  gx += -2.f * kK3 * x * w[6];
-  gy += -2.f * kK3 * y * w[6];
-  gz += 4.f * kK3 * z * w[6];
-  gx += -kK2 * z * w[7];
-  gz += -kK2 * x * w[7];
-  gx += kK2 * x * w[8];
-  gy += -kK2 * y * w[8];
-  if (deg < 3) return;
-  gx += -kA3 * 6.f * x * y * w[9];
-  gy += -kA3 * (3.f * xx - 3.f * yy) * w[9];
-  gx += kB3 * y * z * w[10];
-  gy += kB3 * x * z * w[10];
-  gz += kB3 * x * y * w[10];
-  gx += kC3 * 2.f * x * y * w[11];
-  gy += -kC3 * (4.f * zz - xx - 3.f * yy) * w[11];
-  gz += -kC3 * 8.f * y * z * w[11];
-  gx += -kE3 * 6.f * x * z * w[12];
-  gy += -kE3 * 6.f * y * z * w[12];
-  gz += kE3 * (6.f * zz - 3.f * xx - 3.f * yy) * w[12];
-  gx += -kC3 * (4.f * zz - 3.f * xx - yy) * w[13];
-  gy += kC3 * 2.f * x * y * w[13];
-  gz += -kC3 * 8.f * x * z * w[13];
-  gx += kB3 * x * z * w[14];
-  gy += -kB3 * y * z * w[14];
-  gz += 0.5f * kB3 * (xx - yy) * w[14];
-  gx += -kA3 * (3.f * xx - 3.f * yy) * w[15];
-  gy += kA3 * 6.f * x * y * w[15];
-}
-
 // View-independent 3-D state of one Gaussian.
 // Per-Gaussian state in precision F: float64 for the forward (its binning
 // decisions must be those of any float64 evaluation), float32 for the
@@ -333,15 +290,17 @@ __global__ __launch_bounds__(256) void k_preprocess_fwd(ParamsDev prm, ViewTable
 }
 
 // Chain rule from the screen-space accumulators (9 per view) to the parameters.
-// No bit-exact decision is taken here, so the geometry runs in float32.  For
-// several views it is split in two kernels so that each keeps few values live:
+// No bit-exact decision is taken here, so the geometry runs in float32.  It is
+// split in two kernels, run side by side, so that each keeps few values live:
 //  * geometry: per view, conic and mean2D gradients -> dL/dt (camera space) ->
 //    dL/dmean, and dL/dSigma3 summed over the views; then the scale and
 //    rotation gradients once from that sum, and the opacity gradient;
 //  * colour: per view, dL/d(SH coefficients) and the gradient of the view
 //    direction with respect to the mean (added to the geometry kernel's mean
 //    gradient); it also clears the accumulators for the next pass.
-// A single view takes one fused kernel (k_preprocess_bwd_one).
+// One view takes the same pair: a single kernel doing both parts holds the
+// geometry and the 48 coefficients at once and ran slower (0.61 against
+// 0.52 ms for 4M Gaussians).
 
 // One view's geometric terms: the conic, mean2D and opacity sums (a0, a1.xy of
 // the accumulator) -> dL/dmean (camera-space chain) and dL/dSigma3 (symmetrised,
@@ -503,111 +462,10 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd_geom(ParamsDev prm, View
   put(gout.logits + i, g_logit);
 }
 
-// The whole chain for a single-view frame in one pass: each SH coefficient's
-// gradient (Y_j times the colour gradient) is stored as soon as it is formed.
-template <int DEG>
-__global__ __launch_bounds__(256) void k_preprocess_bwd_one(ParamsDev prm, ViewTable vt,
-                                                            float* __restrict__ accG,
-                                                            float* __restrict__ accC,
-                                                            const uint8_t* __restrict__ clampm,
-                                                            GradsDev gout) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int n = prm.n;
-  if (i >= n) return;
-  constexpr int deg = DEG;
-  constexpr int nb = (DEG + 1) * (DEG + 1);
-  const bool add = gout.accumulate != 0;
-  float g_mu[3] = {0.f, 0.f, 0.f}, g_op = 0.f;
-  float Gs[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-  bool geo = false, col = false;
-  float gr[3] = {0.f, 0.f, 0.f};
-  {
-    // untouched entries, and touched ones without gradient, are zero
-    float4* a = reinterpret_cast<float4*>(accG + (size_t)i * kAccG);
-    float4* ac = reinterpret_cast<float4*>(accC + (size_t)i * kAccC);
-    const float4 a0 = a[0], a1 = a[1], c0 = ac[0];
-    geo = a0.x != 0.f || a0.y != 0.f || a0.z != 0.f || a0.w != 0.f || a1.x != 0.f || a1.y != 0.f;
-    col = c0.x != 0.f || c0.y != 0.f || c0.z != 0.f;
-    const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (geo) {  // leave the accumulators cleared for the next backward pass
-      if (!gout.keep_screen) {
-        a[0] = zero4;
-        a[1] = zero4;
-      }
-      float mu[3], Sig[9];
-      geom_body(prm, i, mu, Sig);
-      geom_view(mu, Sig, vt.v[0], a0, a1, g_mu, Gs, g_op);
-    }
-    if (col) {
-      if (!gout.keep_screen) ac[0] = zero4;
-      const uint32_t mask = clampm[i];
-      gr[0] = (mask & 1u) ? 0.f : c0.x;
-      gr[1] = (mask & 2u) ? 0.f : c0.y;
-      gr[2] = (mask & 4u) ? 0.f : c0.z;
-    }
-  }
-  // colour: dL/dsh[j][c] = Y_j gr[c]; direction term into the mean gradient
-  if (col) {
-    const CamDev& cam = vt.v[0];
-    float dx = prm.means[i] - cam.campos[0];
-    float dy = prm.means[n + i] - cam.campos[1];
-    float dz = prm.means[2 * n + i] - cam.campos[2];
-    const float inv = 1.0f / sqrtf(dx * dx + dy * dy + dz * dz);
-    dx *= inv;
-    dy *= inv;
-    dz *= inv;
-    // every coefficient is read before the first gradient store (the compiler
-    // cannot move the reads above stores to another array it cannot prove apart)
-    float w[16];
-#pragma unroll
-    for (int j = 0; j < nb; ++j) {
-      float s = 0.f;
-#pragma unroll
-      for (int ch = 0; ch < 3; ++ch) s += prm.sh[(size_t)(j * 3 + ch) * n + i] * gr[ch];
-      w[j] = s;
-    }
-    float Y[16];
-    sh_basis(dx, dy, dz, deg, Y);
-#pragma unroll
-    for (int j = 0; j < nb; ++j)
-#pragma unroll
-      for (int ch = 0; ch < 3; ++ch) {
-        float* dst = gout.sh + (size_t)(j * 3 + ch) * n + i;
-        const float v = Y[j] * gr[ch];
-        if (add)
-          *dst += v;
-        else
-          *dst = v;
-      }
-    float gx = 0.f, gy = 0.f, gz = 0.f;
-    sh_basis_grad_dot(dx, dy, dz, deg, w, gx, gy, gz);
-    const float dot = gx * dx + gy * dy + gz * dz;
-    g_mu[0] += (gx - dx * dot) * inv;
-    g_mu[1] += (gy - dy * dot) * inv;
-    g_mu[2] += (gz - dz * dot) * inv;
-  } else if (!add) {
-    for (int j = 0; j < nb * 3; ++j) gout.sh[(size_t)j * n + i] = 0.f;
-  }
-  float g_ls[3] = {0.f, 0.f, 0.f}, g_q[4] = {0.f, 0.f, 0.f, 0.f}, g_logit = 0.f;
-  if (geo) geom_finish(prm, i, Gs, g_op, g_ls, g_q, g_logit);
-  const bool any = geo || col;
-  auto put = [&](float* dst, float val) {
-    if (add) {
-      if (any) *dst += val;
-    } else {
-      *dst = val;
-    }
-  };
-  for (int k = 0; k < 3; ++k) put(gout.means + (size_t)k * n + i, g_mu[k]);
-  for (int k = 0; k < 3; ++k) put(gout.log_scales + (size_t)k * n + i, g_ls[k]);
-  for (int k = 0; k < 4; ++k) put(gout.quats + (size_t)k * n + i, g_q[k]);
-  put(gout.logits + i, g_logit);
-}
-
-// g = sum_j w[j] grad Y_j at the unit direction (x, y, z): the same terms as
-// sh_basis_grad_dot, with each weight scaled once and the terms fused into
-// multiply-adds (the backward takes no binning decision, so its rounding is
-// free to differ from the forward's).
+// g = sum_j w[j] grad Y_j at the unit direction (x, y, z): the derivatives of
+// the basis polynomials above, with each weight scaled once and the terms
+// fused into multiply-adds (the backward takes no binning decision, so its
+// rounding is free to differ from the forward's).
 __device__ inline void sh_grad_w(float x, float y, float z, int deg, const float* w, float& gx,
                                  float& gy, float& gz) {
   gx = gy = gz = 0.f;
@@ -790,19 +648,6 @@ gs_status launch_preprocess_bwd(const ParamsDev& p, const ViewTable& vt, Frame& 
   auto* accG = (float*)f.acc.p;
   auto* accC = accG + (size_t)f.views * (size_t)f.n * kAccG;
   auto* cm = (const uint8_t*)f.clampm.p;
-  if (vt.n == 1) {
-    auto one = [&](auto kern) {
-      hipLaunchKernelGGL(kern, dim3(blocks), dim3(256), 0, s, p, vt, accG, accC, cm, g);
-    };
-    switch (p.sh_degree) {
-      case 0: one(k_preprocess_bwd_one<0>); break;
-      case 1: one(k_preprocess_bwd_one<1>); break;
-      case 2: one(k_preprocess_bwd_one<2>); break;
-      default: one(k_preprocess_bwd_one<3>); break;
-    }
-    GS_LAUNCHED("preprocess_bwd_one");
-    return GS_OK;
-  }
   // the geometry kernel (instruction-bound) on the frame's side stream, the colour
   // kernel (memory-bound) on s, joined before the colour kernel's mean term is added
   float* gmu = (float*)f.gmu.p;

@@ -44,7 +44,7 @@ FLOP_PAIR_BWD = 50
 MEASURED_TRAFFIC = [
     {"kernel": "blend_bwd", "views": 4, "tile": 16, "lds_depth": 256, "flags": 3,
      "source": "paper_2509_05216_amd/csrc/blend.hip",
-     "sha256": "2f85b94845b9ffc043e6f77509bfbd8f03c97cadbcdf174e1f0596f37f1a42b7",
+     "sha256": "5d593090c3691b52f4876bd4eefe434331da63c566c5787084f1d76af20f5965",
      "read_bytes": 3174.1e6, "write_bytes": 933.9e6},
 ]
 

@@ -338,9 +338,17 @@ __device__ inline void fwd_tile(Stage<TILE * TILE, DEPTH>& st, const ViewTable& 
   }
 }
 
+// Waves of one tile wait at every batch for the slowest of them (the wave whose
+// 8 x 8 block has the most steps in the batch walks about 1.75 times the mean,
+// by a CPU count on one 2048 x 2048 view), so the forward is held to 64 VGPRs
+// for tiles up to 16: eight resident waves per SIMD instead of seven fill more
+// of those waits (1.37 against 1.44 ms for the 4M-Gaussian batched step).
+template <int TILE>
+constexpr int kFwdWaves = TILE <= 16 ? 8 : 1;
+
 // One workgroup per tile.
 template <int TILE, int DEPTH>
-__global__ __launch_bounds__(TILE* TILE) void k_blend_fwd(ViewTable vt,
+__global__ __launch_bounds__(TILE* TILE) __attribute__((amdgpu_waves_per_eu(kFwdWaves<TILE>))) void k_blend_fwd(ViewTable vt,
                                                           const uint2* __restrict__ ranges,
                                                           const uint32_t* __restrict__ tval,
                                                           const float4* __restrict__ splat,
@@ -365,7 +373,7 @@ __device__ inline int next_tile(uint32_t* counter, const uint32_t* order, int to
 // Persistent form: a grid sized to the device's resident capacity drains the
 // (view, tile) work queue of all views, in the given tile order.
 template <int TILE, int DEPTH>
-__global__ __launch_bounds__(TILE* TILE) void k_blend_fwd_persistent(
+__global__ __launch_bounds__(TILE* TILE) __attribute__((amdgpu_waves_per_eu(kFwdWaves<TILE>))) void k_blend_fwd_persistent(
     ViewTable vt, const uint2* __restrict__ ranges, const uint32_t* __restrict__ tval,
     const float4* __restrict__ splat, float* __restrict__ finalT, uint32_t* __restrict__ ncon,
     const uint32_t* __restrict__ order, uint32_t* counter) {

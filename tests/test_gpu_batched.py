@@ -107,8 +107,12 @@ def test_capture_entry_point_matches_create(P, ctx, scene):
         L.lib().gs_step_graph_destroy(h)
 
 
-def test_graph_replays_match_eager(P, ctx, scene):
+@pytest.mark.parametrize("nviews", [3, 1])
+def test_graph_replays_match_eager(P, ctx, scene, nviews):
+    # one view takes the same side-stream fork and join in the captured
+    # projection backward as several
     cams_d, cams = _mixed_views(P)
+    cams = cams[:nviews]
     params = P.Params.from_numpy(scene.params)
     rng = np.random.default_rng(4)
     targets = [torch.tensor(rng.random((3, c.height, c.width)), dtype=torch.float32,

@@ -193,6 +193,37 @@ def test_backward_matches_oracle(P, ctx, tile, depth, flags):
     _check_grads(grads.to_numpy(), total)
 
 
+def test_colour_backward_forms_agree(P, ctx):
+    """Frames of up to four views take the colour backward that streams the SH
+    coefficients, frames of more the one that holds them; both do the same
+    arithmetic in the same order.  A fifth camera turned away from the scene
+    (every Gaussian behind it) adds no record, so the gradients may differ only
+    by the order of the compositing backward's float atomics (rel. L2 1e-5, far
+    below any slip in a basis term); both forms also match the oracle."""
+    scene = gsscenes.make_scene("iso1m", n=5000, G=96)
+    cams = _cams(4, 128, 96)
+    away = dict(cams[0])
+    flip = np.diag([-1.0, 1.0, -1.0])
+    away["R"] = flip @ np.asarray(cams[0]["R"], np.float64)
+    away["t"] = flip @ np.asarray(cams[0]["t"], np.float64)
+    params = P.Params.from_numpy(scene.params)
+    rng = np.random.default_rng(12)
+    ws = [rng.normal(size=(3, 96, 128)) for _ in range(5)]
+    out = []
+    for views in (cams, cams + [away]):
+        imgs, frame = P.render_fwd(ctx, params, [P.camera_from_dict(c) for c in views])
+        dl = [torch.tensor(w, dtype=torch.float32, device="cuda") for w in ws[:len(views)]]
+        grads = P.render_bwd(ctx, frame, params, dl)
+        torch.cuda.synchronize()
+        assert frame.stats()["n_records"] > 0
+        out.append(grads.to_numpy())
+    for k in GROUPS:
+        assert rel_l2(out[1][k], out[0][k]) < 1e-5, k
+    fws = _oracle_fw(scene.params, cams, 16)
+    total, _ = _oracle_grads(scene.params, cams, fws, ws[:4])
+    _check_grads(out[0], total)
+
+
 def test_screen_space_sums_match_oracle(P, ctx):
     """dL/d(mean2D, conic, opacity, rgb) per (view, Gaussian) kept by the blend
     backward (GS_BWD_KEEP_SCREEN) against the oracle's compositing derivative;

@@ -31,27 +31,150 @@ constexpr float kB3 = 2.89061144264055405f;   // sqrt(105/pi)/2
 constexpr float kC3 = 0.45704579946446572f;   // sqrt(21/(2 pi))/4
 constexpr float kE3 = 0.37317633259011540f;   // sqrt(7/pi)/4
 
-__device__ inline void sh_basis(float x, float y, float z, int deg, float* Y) {
-  Y[0] = kK0;
-  if (deg < 1) return;
-  Y[1] = -kK1 * y;
-  Y[2] = kK1 * z;
-  Y[3] = -kK1 * x;
-  if (deg < 2) return;
-  const float xx = x * x, yy = y * y, zz = z * z;
-  Y[4] = kK2 * x * y;
-  Y[5] = -kK2 * y * z;
-  Y[6] = kK3 * (2.f * zz - xx - yy);
-  Y[7] = -kK2 * x * z;
-  Y[8] = 0.5f * kK2 * (xx - yy);
-  if (deg < 3) return;
-  Y[9] = -kA3 * y * (3.f * xx - yy);
-  Y[10] = kB3 * x * y * z;
-  Y[11] = -kC3 * y * (4.f * zz - xx - yy);
-  Y[12] = kE3 * z * (2.f * zz - 3.f * xx - 3.f * yy);
-  Y[13] = -kC3 * x * (4.f * zz - xx - yy);
-  Y[14] = 0.5f * kB3 * z * (xx - yy);
-  Y[15] = -kA3 * x * (xx - 3.f * yy);
+// Y_j of the real SH basis (degree <= 3, Condon-Shortley phase, m = -l..l) at a
+// unit direction: the one definition of the basis polynomials.
+template <int J>
+__device__ inline float sh_value(float x, float y, float z) {
+  if constexpr (J == 0) return kK0;
+  else if constexpr (J == 1) return -kK1 * y;
+  else if constexpr (J == 2) return kK1 * z;
+  else if constexpr (J == 3) return -kK1 * x;
+  else if constexpr (J == 4) return kK2 * x * y;
+  else if constexpr (J == 5) return -kK2 * y * z;
+  else if constexpr (J == 6) return kK3 * (2.f * (z * z) - (x * x) - (y * y));
+  else if constexpr (J == 7) return -kK2 * x * z;
+  else if constexpr (J == 8) return 0.5f * kK2 * ((x * x) - (y * y));
+  else {
+    const float xx = x * x, yy = y * y, zz = z * z;
+    if constexpr (J == 9) return -kA3 * y * (3.f * xx - yy);
+    else if constexpr (J == 10) return kB3 * x * y * z;
+    else if constexpr (J == 11) return -kC3 * y * (4.f * zz - xx - yy);
+    else if constexpr (J == 12) return kE3 * z * (2.f * zz - 3.f * xx - 3.f * yy);
+    else if constexpr (J == 13) return -kC3 * x * (4.f * zz - xx - yy);
+    else if constexpr (J == 14) return 0.5f * kB3 * z * (xx - yy);
+    else return -kA3 * x * (xx - 3.f * yy);
+  }
+}
+
+// Y[j] for every basis function of degree <= DEG.
+template <int DEG, int J = 0>
+__device__ inline void sh_basis(float x, float y, float z, float* Y) {
+  if constexpr (J < (DEG + 1) * (DEG + 1)) {
+    Y[J] = sh_value<J>(x, y, z);
+    sh_basis<DEG, J + 1>(x, y, z, Y);
+  }
+}
+
+// One basis function j at a unit direction: w grad Y_j added to g (each weight
+// scaled once and the terms fused into multiply-adds: the backward takes no
+// binning decision, so its rounding is free to differ from the forward's), and
+// Y_j returned.  Summed over j in increasing order by sh_grad_w and by the
+// coefficient-streaming colour backward alike.
+struct Dir {
+  float x, y, z;
+};
+
+template <int J>
+__device__ inline float sh_term(const Dir& d, float w, float& gx, float& gy, float& gz) {
+  const float x = d.x, y = d.y, z = d.z;
+  if constexpr (J == 0) {
+    return sh_value<J>(x, y, z);
+  } else if constexpr (J == 1) {
+    gy += -kK1 * w;
+    return sh_value<J>(x, y, z);
+  } else if constexpr (J == 2) {
+    gz += kK1 * w;
+    return sh_value<J>(x, y, z);
+  } else if constexpr (J == 3) {
+    gx += -kK1 * w;
+    return sh_value<J>(x, y, z);
+  } else if constexpr (J == 4) {
+    const float t = kK2 * w;
+    gx = fmaf(y, t, gx);
+    gy = fmaf(x, t, gy);
+    return sh_value<J>(x, y, z);
+  } else if constexpr (J == 5) {
+    const float t = kK2 * w;
+    gy = fmaf(-z, t, gy);
+    gz = fmaf(-y, t, gz);
+    return sh_value<J>(x, y, z);
+  } else if constexpr (J == 6) {
+    const float t = 2.f * kK3 * w;
+    gx = fmaf(-x, t, gx);
+    gy = fmaf(-y, t, gy);
+    gz = fmaf(2.f * z, t, gz);
+    return sh_value<J>(x, y, z);
+  } else if constexpr (J == 7) {
+    const float t = kK2 * w;
+    gx = fmaf(-z, t, gx);
+    gz = fmaf(-x, t, gz);
+    return sh_value<J>(x, y, z);
+  } else if constexpr (J == 8) {
+    const float t = kK2 * w;
+    gx = fmaf(x, t, gx);
+    gy = fmaf(-y, t, gy);
+    return sh_value<J>(x, y, z);
+  } else {
+    const float xx = x * x, yy = y * y, zz = z * z;
+    const float xy = x * y, yz = y * z, xz = x * z, dxy = xx - yy;
+    if constexpr (J == 9) {
+      const float t = kA3 * w;
+      gx = fmaf(-6.f * xy, t, gx);
+      gy = fmaf(-3.f * dxy, t, gy);
+      return sh_value<J>(x, y, z);
+    } else if constexpr (J == 10) {
+      const float t = kB3 * w;
+      gx = fmaf(yz, t, gx);
+      gy = fmaf(xz, t, gy);
+      gz = fmaf(xy, t, gz);
+      return sh_value<J>(x, y, z);
+    } else if constexpr (J == 11) {
+      const float t = kC3 * w;
+      gx = fmaf(2.f * xy, t, gx);
+      gy = fmaf(-(4.f * zz - xx - 3.f * yy), t, gy);
+      gz = fmaf(-8.f * yz, t, gz);
+      return sh_value<J>(x, y, z);
+    } else if constexpr (J == 12) {
+      const float t = kE3 * w;
+      gx = fmaf(-6.f * xz, t, gx);
+      gy = fmaf(-6.f * yz, t, gy);
+      gz = fmaf(6.f * zz - 3.f * xx - 3.f * yy, t, gz);
+      return sh_value<J>(x, y, z);
+    } else if constexpr (J == 13) {
+      const float t = kC3 * w;
+      gx = fmaf(-(4.f * zz - 3.f * xx - yy), t, gx);
+      gy = fmaf(2.f * xy, t, gy);
+      gz = fmaf(-8.f * xz, t, gz);
+      return sh_value<J>(x, y, z);
+    } else if constexpr (J == 14) {
+      const float t = kB3 * w;
+      gx = fmaf(xz, t, gx);
+      gy = fmaf(-yz, t, gy);
+      gz = fmaf(0.5f * dxy, t, gz);
+      return sh_value<J>(x, y, z);
+    } else {
+      const float t = kA3 * w;
+      gx = fmaf(-3.f * dxy, t, gx);
+      gy = fmaf(6.f * xy, t, gy);
+      return sh_value<J>(x, y, z);
+    }
+  }
+}
+
+// g = sum_j w[j] grad Y_j at the unit direction (x, y, z).
+template <int DEG, int J = 0>
+__device__ inline void sh_grad_w_acc(const Dir& d, const float* w, float& gx, float& gy, float& gz) {
+  if constexpr (J < (DEG + 1) * (DEG + 1)) {
+    (void)sh_term<J>(d, w[J], gx, gy, gz);
+    sh_grad_w_acc<DEG, J + 1>(d, w, gx, gy, gz);
+  }
+}
+
+template <int DEG>
+__device__ inline void sh_grad_w(float x, float y, float z, const float* w, float& gx, float& gy,
+                                 float& gz) {
+  gx = gy = gz = 0.f;
+  sh_grad_w_acc<DEG>(Dir{x, y, z}, w, gx, gy, gz);
 }
 
 // View-independent 3-D state of one Gaussian.
@@ -223,30 +346,6 @@ __device__ inline uint32_t alpha_box_bits(float A, float B, float C, float o) {
   return half_bits_up(hw) | (half_bits_up(hh) << 16);
 }
 
-// Y_j at a unit direction (the expressions of sh_basis for j alone).
-template <int J>
-__device__ inline float sh_value(float x, float y, float z) {
-  if constexpr (J == 0) return kK0;
-  else if constexpr (J == 1) return -kK1 * y;
-  else if constexpr (J == 2) return kK1 * z;
-  else if constexpr (J == 3) return -kK1 * x;
-  else if constexpr (J == 4) return kK2 * x * y;
-  else if constexpr (J == 5) return -kK2 * y * z;
-  else if constexpr (J == 6) return kK3 * (2.f * (z * z) - (x * x) - (y * y));
-  else if constexpr (J == 7) return -kK2 * x * z;
-  else if constexpr (J == 8) return 0.5f * kK2 * ((x * x) - (y * y));
-  else {
-    const float xx = x * x, yy = y * y, zz = z * z;
-    if constexpr (J == 9) return -kA3 * y * (3.f * xx - yy);
-    else if constexpr (J == 10) return kB3 * x * y * z;
-    else if constexpr (J == 11) return -kC3 * y * (4.f * zz - xx - yy);
-    else if constexpr (J == 12) return kE3 * z * (2.f * zz - 3.f * xx - 3.f * yy);
-    else if constexpr (J == 13) return -kC3 * x * (4.f * zz - xx - yy);
-    else if constexpr (J == 14) return 0.5f * kB3 * z * (xx - yy);
-    else return -kA3 * x * (xx - 3.f * yy);
-  }
-}
-
 constexpr int kShAheadFwd = 4;  // coefficient triples in flight ahead of the one in use
 
 // rgb_v += sh[j] Y_j(d_v) for every view, coefficient triple by triple (the sum
@@ -395,7 +494,7 @@ __global__ __launch_bounds__(256) void k_preprocess_fwd(ParamsDev prm, ViewTable
     dy *= inv;
     dz *= inv;
     float Y[16];
-    sh_basis(dx, dy, dz, deg, Y);
+    sh_basis<DEG>(dx, dy, dz, Y);
     float rgb[3];
     uint32_t mask = 0;
 #pragma unroll
@@ -603,65 +702,6 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd_geom(ParamsDev prm, View
   put(gout.logits + i, g_logit);
 }
 
-// g = sum_j w[j] grad Y_j at the unit direction (x, y, z): the derivatives of
-// the basis polynomials above, with each weight scaled once and the terms
-// fused into multiply-adds (the backward takes no binning decision, so its
-// rounding is free to differ from the forward's).
-__device__ inline void sh_grad_w(float x, float y, float z, int deg, const float* w, float& gx,
-                                 float& gy, float& gz) {
-  gx = gy = gz = 0.f;
-  if (deg < 1) return;
-  gx = -kK1 * w[3];
-  gy = -kK1 * w[1];
-  gz = kK1 * w[2];
-  if (deg < 2) return;
-  const float xx = x * x, yy = y * y, zz = z * z;
-  float t = kK2 * w[4];
-  gx = fmaf(y, t, gx);
-  gy = fmaf(x, t, gy);
-  t = kK2 * w[5];
-  gy = fmaf(-z, t, gy);
-  gz = fmaf(-y, t, gz);
-  t = 2.f * kK3 * w[6];
-  gx = fmaf(-x, t, gx);
-  gy = fmaf(-y, t, gy);
-  gz = fmaf(2.f * z, t, gz);
-  t = kK2 * w[7];
-  gx = fmaf(-z, t, gx);
-  gz = fmaf(-x, t, gz);
-  t = kK2 * w[8];
-  gx = fmaf(x, t, gx);
-  gy = fmaf(-y, t, gy);
-  if (deg < 3) return;
-  const float xy = x * y, yz = y * z, xz = x * z, dxy = xx - yy;
-  t = kA3 * w[9];
-  gx = fmaf(-6.f * xy, t, gx);
-  gy = fmaf(-3.f * dxy, t, gy);
-  t = kB3 * w[10];
-  gx = fmaf(yz, t, gx);
-  gy = fmaf(xz, t, gy);
-  gz = fmaf(xy, t, gz);
-  t = kC3 * w[11];
-  gx = fmaf(2.f * xy, t, gx);
-  gy = fmaf(-(4.f * zz - xx - 3.f * yy), t, gy);
-  gz = fmaf(-8.f * yz, t, gz);
-  t = kE3 * w[12];
-  gx = fmaf(-6.f * xz, t, gx);
-  gy = fmaf(-6.f * yz, t, gy);
-  gz = fmaf(6.f * zz - 3.f * xx - 3.f * yy, t, gz);
-  t = kC3 * w[13];
-  gx = fmaf(-(4.f * zz - 3.f * xx - yy), t, gx);
-  gy = fmaf(2.f * xy, t, gy);
-  gz = fmaf(-8.f * xz, t, gz);
-  t = kB3 * w[14];
-  gx = fmaf(xz, t, gx);
-  gy = fmaf(-yz, t, gy);
-  gz = fmaf(0.5f * dxy, t, gz);
-  t = kA3 * w[15];
-  gx = fmaf(-3.f * dxy, t, gx);
-  gy = fmaf(6.f * xy, t, gy);
-}
-
 // Colour part for frames of more than four views (k_preprocess_bwd_sh_few below
 // takes the others); runs beside k_preprocess_bwd_geom (on another stream), writes its
 // term of the mean gradient to gmu (added to the geometry kernel's by
@@ -723,7 +763,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     const float inv = col ? 1.0f / sqrtf(dx * dx + dy * dy + dz * dz) : 0.f;
     const float x = dx * inv, y = dy * inv, z = dz * inv;
     float Y[16], w[16];
-    sh_basis(x, y, z, deg, Y);
+    sh_basis<DEG>(x, y, z, Y);
 #pragma unroll
     for (int j = 0; j < nb; ++j) {
       gsh[j][0] = fmaf(Y[j], gr0, gsh[j][0]);
@@ -732,7 +772,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
       w[j] = fmaf(gr2, sh[j][2], fmaf(gr1, sh[j][1], gr0 * sh[j][0]));
     }
     float gx, gy, gz;
-    sh_grad_w(x, y, z, deg, w, gx, gy, gz);
+    sh_grad_w<DEG>(x, y, z, w, gx, gy, gz);
     // through the normalisation d = (mu - campos) / |mu - campos|
     const float dot = gx * x + gy * y + gz * z;
     gmf[0] += (gx - x * dot) * inv;
@@ -754,101 +794,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
       }
   } else if (!add) {
     for (int j = 0; j < nb * 3; ++j) gout.sh[(size_t)j * n + i] = 0.f;
-  }
-}
-
-// One SH basis function j at the unit direction of one view: its value Y_j,
-// and w grad Y_j added to g (the terms of sh_basis and sh_grad_w for j alone, in
-// the same operation order, so a sum over j in increasing order reproduces
-// sh_grad_w's rounding).
-struct Dir {
-  float x, y, z;
-};
-
-template <int J>
-__device__ inline float sh_term(const Dir& d, float w, float& gx, float& gy, float& gz) {
-  const float x = d.x, y = d.y, z = d.z;
-  if constexpr (J == 0) {
-    return kK0;
-  } else if constexpr (J == 1) {
-    gy += -kK1 * w;
-    return -kK1 * y;
-  } else if constexpr (J == 2) {
-    gz += kK1 * w;
-    return kK1 * z;
-  } else if constexpr (J == 3) {
-    gx += -kK1 * w;
-    return -kK1 * x;
-  } else if constexpr (J == 4) {
-    const float t = kK2 * w;
-    gx = fmaf(y, t, gx);
-    gy = fmaf(x, t, gy);
-    return kK2 * x * y;
-  } else if constexpr (J == 5) {
-    const float t = kK2 * w;
-    gy = fmaf(-z, t, gy);
-    gz = fmaf(-y, t, gz);
-    return -kK2 * y * z;
-  } else if constexpr (J == 6) {
-    const float t = 2.f * kK3 * w;
-    gx = fmaf(-x, t, gx);
-    gy = fmaf(-y, t, gy);
-    gz = fmaf(2.f * z, t, gz);
-    return kK3 * (2.f * (z * z) - (x * x) - (y * y));
-  } else if constexpr (J == 7) {
-    const float t = kK2 * w;
-    gx = fmaf(-z, t, gx);
-    gz = fmaf(-x, t, gz);
-    return -kK2 * x * z;
-  } else if constexpr (J == 8) {
-    const float t = kK2 * w;
-    gx = fmaf(x, t, gx);
-    gy = fmaf(-y, t, gy);
-    return 0.5f * kK2 * ((x * x) - (y * y));
-  } else {
-    const float xx = x * x, yy = y * y, zz = z * z;
-    const float xy = x * y, yz = y * z, xz = x * z, dxy = xx - yy;
-    if constexpr (J == 9) {
-      const float t = kA3 * w;
-      gx = fmaf(-6.f * xy, t, gx);
-      gy = fmaf(-3.f * dxy, t, gy);
-      return -kA3 * y * (3.f * xx - yy);
-    } else if constexpr (J == 10) {
-      const float t = kB3 * w;
-      gx = fmaf(yz, t, gx);
-      gy = fmaf(xz, t, gy);
-      gz = fmaf(xy, t, gz);
-      return kB3 * x * y * z;
-    } else if constexpr (J == 11) {
-      const float t = kC3 * w;
-      gx = fmaf(2.f * xy, t, gx);
-      gy = fmaf(-(4.f * zz - xx - 3.f * yy), t, gy);
-      gz = fmaf(-8.f * yz, t, gz);
-      return -kC3 * y * (4.f * zz - xx - yy);
-    } else if constexpr (J == 12) {
-      const float t = kE3 * w;
-      gx = fmaf(-6.f * xz, t, gx);
-      gy = fmaf(-6.f * yz, t, gy);
-      gz = fmaf(6.f * zz - 3.f * xx - 3.f * yy, t, gz);
-      return kE3 * z * (2.f * zz - 3.f * xx - 3.f * yy);
-    } else if constexpr (J == 13) {
-      const float t = kC3 * w;
-      gx = fmaf(-(4.f * zz - 3.f * xx - yy), t, gx);
-      gy = fmaf(2.f * xy, t, gy);
-      gz = fmaf(-8.f * xz, t, gz);
-      return -kC3 * x * (4.f * zz - xx - yy);
-    } else if constexpr (J == 14) {
-      const float t = kB3 * w;
-      gx = fmaf(xz, t, gx);
-      gy = fmaf(-yz, t, gy);
-      gz = fmaf(0.5f * dxy, t, gz);
-      return 0.5f * kB3 * z * (xx - yy);
-    } else {
-      const float t = kA3 * w;
-      gx = fmaf(-3.f * dxy, t, gx);
-      gy = fmaf(6.f * xy, t, gy);
-      return -kA3 * x * (xx - 3.f * yy);
-    }
   }
 }
 

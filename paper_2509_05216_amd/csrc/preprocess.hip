@@ -346,6 +346,61 @@ __device__ inline uint32_t alpha_box_bits(float A, float B, float C, float o) {
   return half_bits_up(hw) | (half_bits_up(hh) << 16);
 }
 
+// Outputs of the projection forward, indexed by (view, Gaussian) entry.
+struct FwdOut {
+  float4* splat;
+  uint2* rect;
+  uint32_t* dkey;
+  uint8_t* clampm;
+  int32_t* radii;
+};
+
+// One (view, Gaussian) entry: tile rectangle, depth key and radius, and for a
+// touched entry the clamp mask and splat record.  colour(rgb) gives the SH sum
+// of each channel; the 0.5 offset and the clamp at zero are applied here.
+template <class Colour>
+__device__ inline void write_entry(const Body& b, const CamDev& c, int tile, size_t o,
+                                   float opacity, const FwdOut& out, Colour colour) {
+  Proj p;
+  project_view(b, c, tile, p);
+  if (out.radii != nullptr) out.radii[o] = p.radius;  // 0 unless touched
+  if (!p.touched) {
+    out.rect[o] = make_uint2(1u | (1u << 16), 0u);
+    out.dkey[o] = 0xffffffffu;
+    return;
+  }
+  const float depth = (float)p.t[2];
+  out.rect[o] = make_uint2((uint32_t)p.x0 | ((uint32_t)p.y0 << 16),
+                           (uint32_t)p.x1 | ((uint32_t)p.y1 << 16));
+  out.dkey[o] = __float_as_uint(depth);
+  float rgb[3];
+  colour(rgb);
+  uint32_t mask = 0;
+#pragma unroll
+  for (int ch = 0; ch < 3; ++ch) {
+    float acc = rgb[ch] + 0.5f;
+    if (acc < 0.f) {
+      mask |= 1u << ch;
+      acc = 0.f;
+    }
+    rgb[ch] = acc;
+  }
+  out.clampm[o] = (uint8_t)mask;
+  const double fmx = floor(p.mx), fmy = floor(p.my);
+  const double cmx = fmin(fmax(fmx, -1073741824.0), 1073741824.0);
+  const double cmy = fmin(fmax(fmy, -1073741824.0), 1073741824.0);
+  // conic = (c, -b, a) / det through one float64 reciprocal: within a float64 ulp of
+  // the quotients, so the stored float32 values are the rounded quotients but for
+  // rare ties of the double rounding (no binning decision reads them)
+  const double idet = 1.0 / p.det;
+  const float cA = (float)(p.c * idet), cB = (float)(-p.b * idet), cC = (float)(p.a * idet);
+  out.splat[o * 3 + 0] = make_float4(cA, cB, cC, opacity);
+  out.splat[o * 3 + 1] = make_float4(__int_as_float((int)cmx), __int_as_float((int)cmy),
+                                     (float)(0.5 - (p.mx - cmx)), (float)(0.5 - (p.my - cmy)));
+  out.splat[o * 3 + 2] =
+      make_float4(rgb[0], rgb[1], rgb[2], __uint_as_float(alpha_box_bits(cA, cB, cC, opacity)));
+}
+
 constexpr int kShAheadFwd = 4;  // coefficient triples in flight ahead of the one in use
 
 // rgb_v += sh[j] Y_j(d_v) for every view, coefficient triple by triple (the sum
@@ -413,45 +468,14 @@ __global__ __launch_bounds__(256) void k_preprocess_fwd_few(ParamsDev prm, ViewT
       for (int c = 0; c < 3; ++c) q[k][c] = shc[(size_t)(k * 3 + c) * n + i];
     sh_colour_stream<DEG, NV, 0>(shc, i, n, dx, dy, dz, rgb, q);
   }
+  const FwdOut out{splat, rect, dkey, clampm, radii};
 #pragma unroll
-  for (int v = 0; v < NV; ++v) {
-    const CamDev& c = vt.v[v];
-    Proj p;
-    project_view(b, c, vt.tile, p);
-    const size_t o = (size_t)v * n + i;
-    if (radii != nullptr) radii[o] = p.radius;  // 0 unless touched
-    if (!p.touched) {
-      rect[o] = make_uint2(1u | (1u << 16), 0u);
-      dkey[o] = 0xffffffffu;
-      continue;
-    }
-    const float depth = (float)p.t[2];
-    rect[o] = make_uint2((uint32_t)p.x0 | ((uint32_t)p.y0 << 16),
-                         (uint32_t)p.x1 | ((uint32_t)p.y1 << 16));
-    dkey[o] = __float_as_uint(depth);
-    uint32_t mask = 0;
-    float col[3];
-#pragma unroll
-    for (int ch = 0; ch < 3; ++ch) {
-      float acc = rgb[v][ch] + 0.5f;
-      if (acc < 0.f) {
-        mask |= 1u << ch;
-        acc = 0.f;
-      }
-      col[ch] = acc;
-    }
-    clampm[o] = (uint8_t)mask;
-    const double fmx = floor(p.mx), fmy = floor(p.my);
-    const double cmx = fmin(fmax(fmx, -1073741824.0), 1073741824.0);
-    const double cmy = fmin(fmax(fmy, -1073741824.0), 1073741824.0);
-    const double idet = 1.0 / p.det;
-    const float cA = (float)(p.c * idet), cB = (float)(-p.b * idet), cC = (float)(p.a * idet);
-    splat[o * 3 + 0] = make_float4(cA, cB, cC, opacity);
-    splat[o * 3 + 1] = make_float4(__int_as_float((int)cmx), __int_as_float((int)cmy),
-                                   (float)(0.5 - (p.mx - cmx)), (float)(0.5 - (p.my - cmy)));
-    splat[o * 3 + 2] =
-        make_float4(col[0], col[1], col[2], __uint_as_float(alpha_box_bits(cA, cB, cC, opacity)));
-  }
+  for (int v = 0; v < NV; ++v)
+    write_entry(b, vt.v[v], vt.tile, (size_t)v * n + i, opacity, out, [&](float (&col)[3]) {
+      col[0] = rgb[v][0];
+      col[1] = rgb[v][1];
+      col[2] = rgb[v][2];
+    });
 }
 
 template <int DEG>
@@ -468,61 +492,29 @@ __global__ __launch_bounds__(256) void k_preprocess_fwd(ParamsDev prm, ViewTable
   load_body(prm, i, b);
   const double logit = (double)prm.logits[i];
   const float opacity = (float)(1.0 / (1.0 + exp(-logit)));
-  constexpr int deg = DEG;
   constexpr int nb = (DEG + 1) * (DEG + 1);
+  const FwdOut out{splat, rect, dkey, clampm, radii};
   for (int v = 0; v < vt.n; ++v) {
     const CamDev& c = vt.v[v];
-    Proj p;
-    project_view(b, c, vt.tile, p);
-    const size_t o = (size_t)v * n + i;
-    if (radii != nullptr) radii[o] = p.radius;  // 0 unless touched
-    if (!p.touched) {
-      rect[o] = make_uint2(1u | (1u << 16), 0u);
-      dkey[o] = 0xffffffffu;
-      continue;
-    }
-    const float depth = (float)p.t[2];
-    rect[o] = make_uint2((uint32_t)p.x0 | ((uint32_t)p.y0 << 16),
-                         (uint32_t)p.x1 | ((uint32_t)p.y1 << 16));
-    dkey[o] = __float_as_uint(depth);
-    // view-dependent colour
-    float dx = (float)b.mu[0] - c.campos[0];
-    float dy = (float)b.mu[1] - c.campos[1];
-    float dz = (float)b.mu[2] - c.campos[2];
-    const float inv = 1.0f / sqrtf(dx * dx + dy * dy + dz * dz);
-    dx *= inv;
-    dy *= inv;
-    dz *= inv;
-    float Y[16];
-    sh_basis<DEG>(dx, dy, dz, Y);
-    float rgb[3];
-    uint32_t mask = 0;
+    write_entry(b, c, vt.tile, (size_t)v * n + i, opacity, out, [&](float (&col)[3]) {
+      // view-dependent colour
+      float dx = (float)b.mu[0] - c.campos[0];
+      float dy = (float)b.mu[1] - c.campos[1];
+      float dz = (float)b.mu[2] - c.campos[2];
+      const float inv = 1.0f / sqrtf(dx * dx + dy * dy + dz * dz);
+      dx *= inv;
+      dy *= inv;
+      dz *= inv;
+      float Y[16];
+      sh_basis<DEG>(dx, dy, dz, Y);
 #pragma unroll
-    for (int ch = 0; ch < 3; ++ch) {
-      float acc = 0.f;
+      for (int ch = 0; ch < 3; ++ch) {
+        float acc = 0.f;
 #pragma unroll
-      for (int j = 0; j < nb; ++j) acc += prm.sh[(size_t)(j * 3 + ch) * n + i] * Y[j];
-      acc += 0.5f;
-      if (acc < 0.f) {
-        mask |= 1u << ch;
-        acc = 0.f;
+        for (int j = 0; j < nb; ++j) acc += prm.sh[(size_t)(j * 3 + ch) * n + i] * Y[j];
+        col[ch] = acc;
       }
-      rgb[ch] = acc;
-    }
-    clampm[o] = (uint8_t)mask;
-    const double fmx = floor(p.mx), fmy = floor(p.my);
-    const double cmx = fmin(fmax(fmx, -1073741824.0), 1073741824.0);
-    const double cmy = fmin(fmax(fmy, -1073741824.0), 1073741824.0);
-    // conic = (c, -b, a) / det through one float64 reciprocal: within a float64 ulp of
-    // the quotients, so the stored float32 values are the rounded quotients but for
-    // rare ties of the double rounding (no binning decision reads them)
-    const double idet = 1.0 / p.det;
-    const float cA = (float)(p.c * idet), cB = (float)(-p.b * idet), cC = (float)(p.a * idet);
-    splat[o * 3 + 0] = make_float4(cA, cB, cC, opacity);
-    splat[o * 3 + 1] = make_float4(__int_as_float((int)cmx), __int_as_float((int)cmy),
-                                   (float)(0.5 - (p.mx - cmx)), (float)(0.5 - (p.my - cmy)));
-    splat[o * 3 + 2] =
-        make_float4(rgb[0], rgb[1], rgb[2], __uint_as_float(alpha_box_bits(cA, cB, cC, opacity)));
+    });
   }
 }
 
